@@ -1,0 +1,190 @@
+/*
+ * pplbm.h -- C ABI of the MI355X pseudo-potential D2Q9 lattice Boltzmann library.
+ *
+ * The method is that of Hu, Li & Uddin, "Force Method in a Pseudo-potential Lattice
+ * Boltzmann Model" (arXiv:1412.5170).  One time step (lbm_step) is:
+ *   rho = sum_a f_a (Eq. 3) -> psi(rho) from the K-rescaled Carnahan-Starling EOS
+ *   (Eq. 29, Eq. 30, Eq. 7) -> interaction force F (Kupershtokh hybrid, Eq. 6; A = 0 is the
+ *   Shan-Chen force of Eq. 4) -> forcing scheme (exact difference, Eq. 22; Guo, Eq. 23; Guo
+ *   with Li's modified term, Eq. 31) -> BGK (Eq. 1) or MRT (Eq. 34-35) collision ->
+ *   periodic streaming (Eq. 36).
+ * It runs as two HIP kernels for gfx950: a density/psi pass and a fused
+ * force + collide + stream pass.
+ *
+ * Conventions
+ *   - Every function returns LBM_OK (0) or a negative LBM_E* code; no exception crosses
+ *     the ABI.  lbm_last_error() gives the text of the last failure on a handle.
+ *   - Host arrays belong to the caller, are FP64, row-major with x fastest: index y*nx + x.
+ *     A velocity array holds the pair (u_x, u_y) per node: index 2*(y*nx + x) + {0, 1}.
+ *   - Device state: populations are FP32, nine SoA planes per buffer, plane a at
+ *     a * plane_floats, node (x, y) at y * pitch + x inside a plane.  Two population
+ *     buffers (read and write side of the step) and one psi plane (ny * pitch floats).
+ *     They belong to the handle unless lbm_attach supplied them; attached memory must
+ *     outlive the handle.
+ *   - Ordering of the nine velocities: e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0),
+ *     e_4 = (0,-1), e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1).
+ *   - lbm_step and lbm_init are asynchronous on the handle's stream; lbm_read, lbm_stats and
+ *     lbm_populations synchronise it.  One handle per stream; calls on one handle must not
+ *     overlap.
+ */
+#ifndef PPLBM_H
+#define PPLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)        /* invalid argument or unsupported combination            */
+#define LBM_ENOMEM (-2)        /* host or device allocation failed                       */
+#define LBM_EHIP (-3)          /* a HIP runtime call failed (text in lbm_last_error)     */
+#define LBM_EUNSTABLE (-4)     /* non-finite state, psi^2 <= 0 or b rho / 4 >= 1         */
+#define LBM_ENOTCONVERGED (-5) /* step cap reached before the convergence criterion     */
+#define LBM_ESTATE (-6)        /* call out of order (e.g. step before init)              */
+
+/* ---- physics parameters ----------------------------------------------------------------- */
+enum { LBM_EOS_CARNAHAN_STARLING = 0 };
+enum { LBM_FORCE_EDM = 0, LBM_FORCE_GUO = 1, LBM_FORCE_GUO_LI = 2 };
+enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
+/* Arithmetic precision of the kernels; the populations are stored in FP32 either way. */
+enum { LBM_PREC_F32 = 0, LBM_PREC_F64 = 1 };
+
+/* Equation of state, Eq. 29-30: p = K (rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3 - a rho^2),
+ * eta = b rho / 4.  T is given relative to the exact critical temperature of Eq. 29
+ * (dp/drho = d2p/drho2 = 0).  Paper values: a = 1, b = 4, R = 1 (Sec. 4.1). */
+typedef struct {
+    int kind;          /* LBM_EOS_CARNAHAN_STARLING */
+    double a, b, R;
+    double T_over_Tc;  /* reduced temperature, 0 < T/Tc < 1 for two phases */
+    double K;          /* EOS rescale of Eq. 30, K > 0 */
+} lbm_eos;
+
+/* Interaction force and forcing scheme.
+ *   F = -A sum_a w(|e_a|^2) U(x+e_a) e_a - (1-A) G psi(x) sum_a w(|e_a|^2) psi(x+e_a) e_a,
+ *   U = G psi^2 / 2, w(1) = 1/3, w(2) = 1/12 (Eq. 4-6).  psi from p0 = rho/3 + G psi^2/2
+ *   (Eq. 7), so G must be negative; the force does not depend on G except through Li's term.
+ * scheme: LBM_FORCE_EDM (Eq. 22), LBM_FORCE_GUO (Eq. 23), LBM_FORCE_GUO_LI (Eq. 31: Guo's
+ * term with v' = v + sigma F / ((tau - 1/2) psi^2); Eq. 32 gives eps = 16 sigma for G = -1). */
+typedef struct {
+    int scheme;
+    double A;      /* Kupershtokh hybrid weight; A = 0 is Eq. 4, A = 1 is Eq. 5 */
+    double sigma;  /* Li's constant (LBM_FORCE_GUO_LI only) */
+    double G;      /* interaction strength, < 0; the paper uses G = -1 (Sec. 4.3) */
+} lbm_force;
+
+/* Collision.  BGK: Eq. 1 with relaxation time tau.  MRT (Eq. 34-35): Lallemand-Luo moment
+ * basis in the order (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy), Lambda =
+ * diag(s_rho, s_e, s_eps, s_j, s_q, s_j, s_q, 1/tau, 1/tau); Guo's source in moment space;
+ * with LBM_FORCE_GUO_LI, Li's extra stress 2 sigma F F / psi^2 enters each stress/energy
+ * moment divided by (1/s_k - 1/2), which reduces exactly to Eq. 31 when every rate is 1/tau.
+ * MRT requires LBM_FORCE_GUO or LBM_FORCE_GUO_LI. */
+typedef struct {
+    int kind;      /* LBM_COLL_BGK or LBM_COLL_MRT */
+    double s_rho, s_e, s_eps, s_j, s_q;  /* MRT rates in (0, 2); ignored for BGK */
+} lbm_collision;
+
+/* Observables of Sec. 4 (Tables 3-7), reduced in FP64 in a fixed order (deterministic). */
+typedef struct {
+    double mass;        /* sum over nodes of rho */
+    double rho_min, rho_max;
+    double rho_probe_a; /* rho at probe node a (default: lattice centre) */
+    double rho_probe_b; /* rho at probe node b (default: node (0, 0)) */
+    double ratio;       /* max(rho_probe_a, rho_probe_b) / min(...) */
+    double us_max;      /* max over nodes of |v|, v = u + F / (2 rho) */
+    double dv_max;      /* max over nodes of |v - v_prev|_inf since the previous tracked call */
+    long long step;     /* time steps taken since lbm_init */
+    int nonfinite;      /* number of nodes with a non-finite rho or v, or undefined psi */
+} lbm_stats_t;
+
+typedef struct lbm lbm_t;
+
+/* Create a handle for an nx x ny periodic lattice.  Validates the parameters (nx, ny >= 1,
+ * tau > 1/2, G < 0, b > 0, K > 0, 0 < T/Tc, MRT only with Guo/Guo+Li, MRT rates in (0, 2))
+ * and computes the absolute temperature; allocates no device memory.  *out receives the
+ * handle (NULL on error). */
+int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+               const lbm_collision *collision, double tau, lbm_t **out);
+
+/* Release the handle and any device memory it owns. */
+void lbm_destroy(lbm_t *h);
+
+/* Device layout the handle uses: row pitch in floats (>= nx), floats per population plane,
+ * bytes of one population buffer (9 planes) and of the psi plane.  Any pointer may be NULL. */
+int lbm_layout(const lbm_t *h, size_t *pitch_floats, size_t *plane_floats, size_t *f_bytes,
+               size_t *psi_bytes);
+
+/* Hand the handle caller-owned device memory (e.g. from torch): two population buffers of
+ * f_bytes each and a psi plane of psi_bytes, all 256-byte aligned, plus the HIP stream
+ * (hipStream_t, NULL for the default stream).  Replaces any memory the handle owned. */
+int lbm_attach(lbm_t *h, void *f_a, void *f_b, void *psi, void *stream);
+
+/* Select the stream later calls are issued on (hipStream_t, NULL = default stream). */
+int lbm_set_stream(lbm_t *h, void *stream);
+
+/* Arithmetic precision of the kernels (LBM_PREC_F32 or LBM_PREC_F64, the default).  The
+ * populations stay FP32 in memory either way, so the HBM traffic is the same; FP64 arithmetic
+ * keeps the FP32-stored state within 1e-5 of an FP64 run after 100 steps, FP32 arithmetic
+ * roughly doubles that error. */
+int lbm_set_precision(lbm_t *h, int precision);
+
+/* Tile of the fused pass: tx x ty threads per workgroup (tx a multiple of 64, tx * ty <= 1024).
+ * Results do not depend on the tile. */
+int lbm_set_tile(lbm_t *h, int tx, int ty);
+
+/* Probe nodes reported by lbm_stats (defaults: a = (nx/2, ny/2), b = (0, 0)). */
+int lbm_set_probes(lbm_t *h, int xa, int ya, int xb, int yb);
+
+/* Initial state f_a = f^eq_a(rho0, u0) (Eq. 2) from host FP64 fields; u0 may be NULL (rest).
+ * Allocates the device buffers on first use if none were attached.  Resets the step count. */
+int lbm_init(lbm_t *h, const double *rho0, const double *u0);
+
+/* Advance n >= 0 time steps (Sec. 2-4; Eq. 1 or Eq. 34-36), asynchronously. */
+int lbm_step(lbm_t *h, int n);
+
+/* Density (Eq. 3) and actual fluid velocity v = u + F/(2 rho) (Sec. 3.2) of the current
+ * state into host FP64 arrays (either may be NULL).  Synchronises the stream. */
+int lbm_read(lbm_t *h, double *rho, double *u);
+
+/* Current populations as FP32 host array [9][ny][nx] (velocity order above). Synchronises. */
+int lbm_populations(lbm_t *h, float *f);
+
+/* Replace the populations from a host FP32 array [9][ny][nx]; keeps the step count. */
+int lbm_set_populations(lbm_t *h, const float *f);
+
+/* FP64 observables of the current state.  track_dv != 0 also compares v with the velocity
+ * stored by the previous tracked call (dv_max; 0 on the first) and stores the current one.
+ * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. Synchronises. */
+int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around every launch of
+ * the two step kernels while enabled.  lbm_timing returns the summed milliseconds of the
+ * density/psi pass and of the fused pass and the number of steps timed, then resets them. */
+int lbm_timing_enable(lbm_t *h, int enable);
+int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps);
+
+/* ---- EOS helpers (host only) -------------------------------------------------------------- */
+
+/* Exact critical point of Eq. 29 (independent of K): dp/drho = d2p/drho2 = 0. */
+int lbm_eos_critical(const lbm_eos *eos, double *rho_c, double *T_c, double *p_c);
+
+/* Maxwell equal-area coexistence densities (Eq. 19) at eos->T_over_Tc; independent of K
+ * (Sec. 4.1).  Solved as equal pressure and equal chemical potential of the two phases with
+ * the Carnahan-Starling free energy. */
+int lbm_eos_maxwell(const lbm_eos *eos, double *rho_g, double *rho_l);
+
+/* ---- error text ----------------------------------------------------------------------------- */
+const char *lbm_strerror(int code);
+const char *lbm_last_error(const lbm_t *h);
+
+/* ---- measurement aid ----------------------------------------------------------------------- */
+/* Copy n floats src -> dst (device pointers) with a plain streaming kernel on `stream`.
+ * Its HBM counters give the scale factor for the library's own kernels' counters. */
+int lbm_copy_f32(float *dst, const float *src, size_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPLBM_H */

@@ -72,7 +72,13 @@ def lib():
         _lib.orc_psi.argtypes = [pp, ctypes.c_double]
         _lib.orc_psi.restype = ctypes.c_double
         _lib.orc_mrt_matrix.argtypes = [dp, dp]
+        _lib.orc_threads.restype = ctypes.c_int
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the stepper runs on."""
+    return int(lib().orc_threads())
 
 
 class OracleError(RuntimeError):

@@ -440,3 +440,11 @@ int orc_mrt_matrix(double *M_out, double *Minv_out)
         }
     return ORC_OK;
 }
+
+/* Number of OpenMP threads the stepper's parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

@@ -1,0 +1,556 @@
+// C ABI runtime of the pseudo-potential D2Q9 lattice Boltzmann library (include/pplbm.h):
+// parameter validation, Carnahan-Starling critical point and Maxwell densities on the host,
+// device buffers, the time-step launch sequence and the read-back paths.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pplbm.h"
+#include "lbm_internal.h"
+
+using pplbm::Physics;
+
+struct lbm {
+    Physics p{};
+    lbm_eos eos{};
+    lbm_force force{};
+    lbm_collision coll{};
+    double tau = 1.0, T = 0.0;
+    float *f[2] = {nullptr, nullptr};
+    float *psi = nullptr;
+    bool owned = false;
+    int cur = 0;  // index of the buffer holding the current populations
+    hipStream_t stream = nullptr;
+    bool fp64 = true;  // FP64 arithmetic, FP32 storage (see lbm_set_precision)
+    int tx = 64, ty = 4;
+    int xa = 0, ya = 0, xb = 0, yb = 0;
+    long long step = 0;
+    bool initialised = false;
+    float *vprev = nullptr;
+    bool vprev_valid = false;
+    double *stats_partial = nullptr;
+    double *stats_out = nullptr;
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // 3 per timed step
+    size_t events_used = 0;
+    long long timed_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(lbm *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(lbm *h, hipError_t e, const char *what) {
+    if (h) h->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EHIP;
+}
+
+#define HIP_TRY(h, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+// ---- Carnahan-Starling EOS on the host (Eq. 29-30), written in eta = b rho / 4 ----------
+// p(eta) = K [ (4 R T / b) h(eta) - (16 a / b^2) eta^2 ],  h = eta Z(eta),
+// Z = (1 + eta + eta^2 - eta^3) / (1 - eta)^3.
+struct CS {
+    double a, b, R, K;
+    double dpdrho(double rho, double T) const {
+        // d(rho Z)/drho = Z + eta Z',  Z' = (4 + 4 eta - 2 eta^2) / (1 - eta)^4
+        const double eta = b * rho / 4.0, om = 1.0 - eta;
+        const double Z = (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om);
+        const double dZ = (4.0 + 4.0 * eta - 2.0 * eta * eta) / (om * om * om * om);
+        return K * (R * T * (Z + eta * dZ) - 2.0 * a * rho);
+    }
+    double p(double rho, double T) const {
+        const double eta = b * rho / 4.0, om = 1.0 - eta;
+        const double Z = (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om);
+        return K * (rho * R * T * Z - a * rho * rho);
+    }
+    // Gibbs energy per particle up to a constant, from the Helmholtz energy per particle
+    // R T (ln rho - 1 + (4 eta - 3 eta^2)/(1 - eta)^2) - a rho (whose rho^2 d/drho is p / K).
+    double g(double rho, double T) const {
+        const double eta = b * rho / 4.0, om = 1.0 - eta;
+        const double f = R * T * (std::log(rho) - 1.0 + (4.0 * eta - 3.0 * eta * eta) / (om * om)) - a * rho;
+        return K * f + p(rho, T) / rho;
+    }
+};
+
+// Critical point: with h(eta) = N / (1 - eta)^3, N = eta + eta^2 + eta^3 - eta^4,
+// dp/deta = 0 and d2p/deta2 = 0 give h'(eta) = eta h''(eta) (independent of a, b, R) and
+// T_c = 8 a / (b R h''(eta_c)).
+void critical(double a, double b, double R, double *rho_c, double *T_c, double *p_c) {
+    auto h1 = [](double e) {
+        const double N = e + e * e + e * e * e - e * e * e * e, N1 = 1 + 2 * e + 3 * e * e - 4 * e * e * e;
+        const double D = 1 - e;
+        return N1 / (D * D * D) + 3 * N / (D * D * D * D);
+    };
+    auto h2 = [](double e) {
+        const double N = e + e * e + e * e * e - e * e * e * e, N1 = 1 + 2 * e + 3 * e * e - 4 * e * e * e;
+        const double N2 = 2 + 6 * e - 12 * e * e, D = 1 - e;
+        return N2 / (D * D * D) + 6 * N1 / (D * D * D * D) + 12 * N / (D * D * D * D * D);
+    };
+    double lo = 0.05, hi = 0.3;  // g(lo) > 0 > g(hi) for g = h' - eta h''
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (h1(mid) - mid * h2(mid) > 0) lo = mid; else hi = mid;
+    }
+    const double ec = 0.5 * (lo + hi);
+    const double Tc = 8.0 * a / (b * R * h2(ec));
+    const double rc = 4.0 * ec / b;
+    CS cs{a, b, R, 1.0};
+    if (rho_c) *rho_c = rc;
+    if (T_c) *T_c = Tc;
+    if (p_c) *p_c = cs.p(rc, Tc);
+}
+
+// Root of an increasing function on [lo, hi] by bisection to the last bit.
+template <typename F>
+double bisect_up(F fn, double lo, double hi) {
+    for (int it = 0; it < 300; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (fn(mid) < 0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+int maxwell(const lbm_eos &e, double *rho_g, double *rho_l) {
+    double rc, Tc, pc;
+    critical(e.a, e.b, e.R, &rc, &Tc, &pc);
+    const double T = e.T_over_Tc * Tc;
+    const CS cs{e.a, e.b, e.R, 1.0};  // the densities do not depend on K
+    const double rmax = 4.0 / e.b;
+    auto dp = [&](double r) { return cs.dpdrho(r, T); };
+    // Spinodals: local maximum below rho_c and local minimum above it.
+    const double s1 = bisect_up([&](double r) { return -dp(r); }, 1e-9 * rmax, rc);
+    const double s2 = bisect_up(dp, rc, 0.999 * rmax);
+    if (!(s1 < s2) || !(dp(0.5 * (s1 + s2)) < 0)) return LBM_EINVAL;
+    const double plo = std::fmax(cs.p(s2, T), 0.0), phi = cs.p(s1, T);
+    auto branches = [&](double P, double *g, double *l) {
+        *g = bisect_up([&](double r) { return cs.p(r, T) - P; }, 1e-300, s1);
+        double hi = s2 + 0.5 * (rmax - s2);
+        while (cs.p(hi, T) < P) hi = rmax - 0.5 * (rmax - hi);
+        *l = bisect_up([&](double r) { return cs.p(r, T) - P; }, s2, hi);
+    };
+    // Equal chemical potential: g(rho_g) - g(rho_l) rises with the trial pressure (at the low
+    // end rho_g -> 0 and its ln rho_g -> -inf).
+    double g = 0, l = 0;
+    const double P = bisect_up([&](double P) {
+        double gg, ll;
+        branches(P, &gg, &ll);
+        return cs.g(gg, T) - cs.g(ll, T);
+    }, plo + 1e-15 * phi, phi * (1 - 1e-12));
+    branches(P, &g, &l);
+    *rho_g = g;
+    *rho_l = l;
+    return LBM_OK;
+}
+
+int validate(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+             const lbm_collision *coll, double tau, std::string *why) {
+    auto bad = [&](const char *m) { *why = m; return LBM_EINVAL; };
+    if (!eos || !force || !coll) return bad("null parameter struct");
+    if (nx < 1 || ny < 1) return bad("nx and ny must be >= 1");
+    if ((double)nx * (double)ny > 4.0e9) return bad("lattice too large");
+    if (!(tau > 0.5) || !std::isfinite(tau)) return bad("tau must be > 1/2");
+    if (eos->kind != LBM_EOS_CARNAHAN_STARLING) return bad("unknown EOS kind");
+    if (!(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0) || !(eos->K > 0))
+        return bad("EOS constants a, b, R, K must be positive");
+    if (!(eos->T_over_Tc > 0) || !std::isfinite(eos->T_over_Tc)) return bad("T/Tc must be positive");
+    if (!(force->G < 0)) return bad("G must be negative (Eq. 7 needs 2 U / G > 0)");
+    if (force->scheme < LBM_FORCE_EDM || force->scheme > LBM_FORCE_GUO_LI) return bad("unknown forcing scheme");
+    if (!std::isfinite(force->A) || !std::isfinite(force->sigma)) return bad("A and sigma must be finite");
+    if (coll->kind != LBM_COLL_BGK && coll->kind != LBM_COLL_MRT) return bad("unknown collision");
+    if (coll->kind == LBM_COLL_MRT) {
+        if (force->scheme == LBM_FORCE_EDM) return bad("MRT is defined with Guo's forcing only");
+        const double r[5] = {coll->s_rho, coll->s_e, coll->s_eps, coll->s_j, coll->s_q};
+        for (double s : r)
+            if (!(s > 0 && s < 2)) return bad("MRT rates must lie in (0, 2)");
+    }
+    return LBM_OK;
+}
+
+int ensure_buffers(lbm *h) {
+    if (h->f[0]) return LBM_OK;
+    size_t fb, pb;
+    lbm_layout(h, nullptr, nullptr, &fb, &pb);
+    void *a = nullptr, *b = nullptr, *c = nullptr;
+    if (hipMalloc(&a, fb) != hipSuccess || hipMalloc(&b, fb) != hipSuccess ||
+        hipMalloc(&c, pb) != hipSuccess) {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (c) (void)hipFree(c);
+        (void)hipGetLastError();
+        return fail(h, LBM_ENOMEM, "device allocation of the lattice buffers failed");
+    }
+    h->f[0] = (float *)a;
+    h->f[1] = (float *)b;
+    h->psi = (float *)c;
+    h->owned = true;
+    // Padding columns are never read; clear them once so copies of the planes are defined.
+    HIP_TRY(h, hipMemsetAsync(a, 0, fb, h->stream));
+    HIP_TRY(h, hipMemsetAsync(b, 0, fb, h->stream));
+    HIP_TRY(h, hipMemsetAsync(c, 0, pb, h->stream));
+    return LBM_OK;
+}
+
+void release_buffers(lbm *h) {
+    if (h->owned) {
+        (void)hipFree(h->f[0]);
+        (void)hipFree(h->f[1]);
+        (void)hipFree(h->psi);
+    }
+    h->f[0] = h->f[1] = h->psi = nullptr;
+    h->owned = false;
+}
+
+int ensure_stats(lbm *h) {
+    if (h->stats_partial) return LBM_OK;
+    const size_t n = pplbm::stats_partial_count(h->p) * pplbm::kStatsFields;
+    if (hipMalloc(&h->stats_partial, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->stats_out, pplbm::kStatsOut * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, LBM_ENOMEM, "device allocation of the reduction buffers failed");
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+               const lbm_collision *collision, double tau, lbm_t **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(nx, ny, eos, force, collision, tau, &why);
+    if (rc) return rc;
+    lbm *h = new (std::nothrow) lbm();
+    if (!h) return LBM_ENOMEM;
+    h->eos = *eos;
+    h->force = *force;
+    h->coll = *collision;
+    h->tau = tau;
+    double rc_, Tc, pc;
+    critical(eos->a, eos->b, eos->R, &rc_, &Tc, &pc);
+    h->T = eos->T_over_Tc * Tc;
+    Physics &p = h->p;
+    p.nx = nx;
+    p.ny = ny;
+    p.pitch = ((size_t)nx + 63) / 64 * 64;
+    p.plane = p.pitch * (size_t)ny;
+    p.b_quarter = eos->b / 4.0;
+    p.RT = eos->R * h->T;
+    p.a = eos->a;
+    p.K = eos->K;
+    p.G = force->G;
+    p.A = force->A;
+    p.sigma = force->scheme == LBM_FORCE_GUO_LI ? force->sigma : 0.0;
+    p.tau = tau;
+    p.scheme = force->scheme;
+    p.coll = collision->kind;
+    const double snu = 1.0 / tau;
+    if (collision->kind == LBM_COLL_MRT) {
+        const double s[9] = {collision->s_rho, collision->s_e, collision->s_eps, collision->s_j,
+                             collision->s_q, collision->s_j, collision->s_q, snu, snu};
+        std::memcpy(p.s, s, sizeof s);
+    } else {
+        for (double &s : p.s) s = snu;
+    }
+    h->xa = nx / 2;
+    h->ya = ny / 2;
+    *out = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_t *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    release_buffers(h);
+    if (h->vprev) (void)hipFree(h->vprev);
+    if (h->stats_partial) (void)hipFree(h->stats_partial);
+    if (h->stats_out) (void)hipFree(h->stats_out);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    delete h;
+}
+
+int lbm_layout(const lbm_t *h, size_t *pitch_floats, size_t *plane_floats, size_t *f_bytes,
+               size_t *psi_bytes) {
+    if (!h) return LBM_EINVAL;
+    if (pitch_floats) *pitch_floats = h->p.pitch;
+    if (plane_floats) *plane_floats = h->p.plane;
+    if (f_bytes) *f_bytes = 9 * h->p.plane * sizeof(float);
+    if (psi_bytes) *psi_bytes = h->p.plane * sizeof(float);
+    return LBM_OK;
+}
+
+int lbm_attach(lbm_t *h, void *f_a, void *f_b, void *psi, void *stream) {
+    if (!h) return LBM_EINVAL;
+    if (!f_a || !f_b || !psi || f_a == f_b) return fail(h, LBM_EINVAL, "attach needs three distinct buffers");
+    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)psi) & 255)
+        return fail(h, LBM_EINVAL, "attached buffers must be 256-byte aligned");
+    release_buffers(h);
+    h->f[0] = (float *)f_a;
+    h->f[1] = (float *)f_b;
+    h->psi = (float *)psi;
+    h->owned = false;
+    h->stream = (hipStream_t)stream;
+    h->cur = 0;
+    h->initialised = false;
+    return LBM_OK;
+}
+
+int lbm_set_stream(lbm_t *h, void *stream) {
+    if (!h) return LBM_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return LBM_OK;
+}
+
+int lbm_set_precision(lbm_t *h, int precision) {
+    if (!h) return LBM_EINVAL;
+    if (precision != LBM_PREC_F32 && precision != LBM_PREC_F64)
+        return fail(h, LBM_EINVAL, "precision must be LBM_PREC_F32 or LBM_PREC_F64");
+    h->fp64 = precision == LBM_PREC_F64;
+    return LBM_OK;
+}
+
+int lbm_set_tile(lbm_t *h, int tx, int ty) {
+    if (!h) return LBM_EINVAL;
+    if (tx < 64 || tx % 64 || ty < 1 || tx * ty > 1024)
+        return fail(h, LBM_EINVAL, "tile: tx a multiple of 64, ty >= 1, tx * ty <= 1024");
+    h->tx = tx;
+    h->ty = ty;
+    return LBM_OK;
+}
+
+int lbm_set_probes(lbm_t *h, int xa, int ya, int xb, int yb) {
+    if (!h) return LBM_EINVAL;
+    if (xa < 0 || xa >= h->p.nx || xb < 0 || xb >= h->p.nx || ya < 0 || ya >= h->p.ny || yb < 0 ||
+        yb >= h->p.ny)
+        return fail(h, LBM_EINVAL, "probe outside the lattice");
+    h->xa = xa;
+    h->ya = ya;
+    h->xb = xb;
+    h->yb = yb;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_t *h, const double *rho0, const double *u0) {
+    if (!h || !rho0) return LBM_EINVAL;
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    for (size_t k = 0; k < N; ++k) {
+        const double eta = h->eos.b * rho0[k] / 4.0;
+        if (!(rho0[k] > 0) || !(eta < 1)) return fail(h, LBM_EUNSTABLE, "initial density outside (0, 4/b)");
+        if (u0 && (!std::isfinite(u0[2 * k]) || !std::isfinite(u0[2 * k + 1])))
+            return fail(h, LBM_EINVAL, "non-finite initial velocity");
+    }
+    int rc = ensure_buffers(h);
+    if (rc) return rc;
+    double *d = nullptr;
+    const size_t bytes = N * sizeof(double) * (u0 ? 3 : 1);
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, LBM_ENOMEM, "staging allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(d, rho0, N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && u0)
+        e = hipMemcpyAsync(d + N, u0, 2 * N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = pplbm::launch_init(h->p, d, u0 ? d + N : nullptr, h->f[0], h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(h, e, "lbm_init");
+    h->cur = 0;
+    h->step = 0;
+    h->initialised = true;
+    h->vprev_valid = false;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_t *h, int n) {
+    if (!h || n < 0) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_step before lbm_init");
+    for (int it = 0; it < n; ++it) {
+        float *fc = h->f[h->cur], *fn = h->f[1 - h->cur];
+        hipEvent_t *ev = nullptr;
+        if (h->timing) {
+            if (h->events_used + 3 > h->events.size()) {
+                for (int k = 0; k < 3 * 64; ++k) {
+                    hipEvent_t e;
+                    HIP_TRY(h, hipEventCreate(&e));
+                    h->events.push_back(e);
+                }
+            }
+            ev = &h->events[h->events_used];
+            h->events_used += 3;
+            HIP_TRY(h, hipEventRecord(ev[0], h->stream));
+        }
+        HIP_TRY(h, pplbm::launch_psi(h->p, h->fp64, fc, h->psi, h->stream));
+        if (ev) HIP_TRY(h, hipEventRecord(ev[1], h->stream));
+        HIP_TRY(h, pplbm::launch_fused(h->p, h->fp64, h->tx, h->ty, fc, h->psi, fn, h->stream));
+        if (ev) {
+            HIP_TRY(h, hipEventRecord(ev[2], h->stream));
+            ++h->timed_steps;
+        }
+        h->cur = 1 - h->cur;
+        ++h->step;
+    }
+    return LBM_OK;
+}
+
+int lbm_read(lbm_t *h, double *rho, double *u) {
+    if (!h) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_read before lbm_init");
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    double *d = nullptr;
+    if (hipMalloc(&d, 3 * N * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, LBM_ENOMEM, "staging allocation failed");
+    }
+    float *fc = h->f[h->cur];
+    hipError_t e = pplbm::launch_psi(h->p, true, fc, h->psi, h->stream);
+    if (e == hipSuccess) e = pplbm::launch_macro(h->p, fc, h->psi, d, d + N, h->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + N, 2 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(h, e, "lbm_read");
+    return LBM_OK;
+}
+
+int lbm_populations(lbm_t *h, float *f) {
+    if (!h || !f) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_populations before lbm_init");
+    const Physics &p = h->p;
+    const float *src = h->f[h->cur];
+    for (int q = 0; q < 9; ++q)
+        HIP_TRY(h, hipMemcpy2DAsync(f + (size_t)q * p.nx * p.ny, p.nx * sizeof(float),
+                                    src + q * p.plane, p.pitch * sizeof(float), p.nx * sizeof(float),
+                                    p.ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_t *h, const float *f) {
+    if (!h || !f) return LBM_EINVAL;
+    int rc = ensure_buffers(h);
+    if (rc) return rc;
+    const Physics &p = h->p;
+    float *dst = h->f[h->cur];
+    for (int q = 0; q < 9; ++q)
+        HIP_TRY(h, hipMemcpy2DAsync(dst + q * p.plane, p.pitch * sizeof(float),
+                                    f + (size_t)q * p.nx * p.ny, p.nx * sizeof(float),
+                                    p.nx * sizeof(float), p.ny, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->initialised = true;
+    h->vprev_valid = false;
+    return LBM_OK;
+}
+
+int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out) {
+    if (!h || !out) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_stats before lbm_init");
+    int rc = ensure_stats(h);
+    if (rc) return rc;
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    if (track_dv && !h->vprev) {
+        if (hipMalloc(&h->vprev, 2 * N * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, LBM_ENOMEM, "allocation of the velocity history failed");
+        }
+        h->vprev_valid = false;
+    }
+    float *fc = h->f[h->cur];
+    HIP_TRY(h, pplbm::launch_psi(h->p, true, fc, h->psi, h->stream));
+    HIP_TRY(h, pplbm::launch_stats(h->p, fc, h->psi, track_dv ? h->vprev : nullptr, h->stats_partial,
+                                   h->stats_out, h->xa, h->ya, h->xb, h->yb, h->stream));
+    double r[pplbm::kStatsOut];
+    HIP_TRY(h, hipMemcpyAsync(r, h->stats_out, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->mass = r[0];
+    out->rho_min = r[1];
+    out->rho_max = r[2];
+    out->us_max = r[3];
+    out->dv_max = (track_dv && h->vprev_valid) ? r[4] : 0.0;
+    out->nonfinite = (int)r[5];
+    out->rho_probe_a = r[6];
+    out->rho_probe_b = r[7];
+    const double hi = std::fmax(r[6], r[7]), lo = std::fmin(r[6], r[7]);
+    out->ratio = hi / lo;
+    out->step = h->step;
+    if (track_dv) h->vprev_valid = true;
+    if (out->nonfinite) return fail(h, LBM_EUNSTABLE, "non-finite or undefined state at some node");
+    return LBM_OK;
+}
+
+int lbm_timing_enable(lbm_t *h, int enable) {
+    if (!h) return LBM_EINVAL;
+    h->timing = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps) {
+    if (!h) return LBM_EINVAL;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    double a = 0, b = 0;
+    for (size_t k = 0; k + 3 <= h->events_used; k += 3) {
+        float t1 = 0, t2 = 0;
+        HIP_TRY(h, hipEventElapsedTime(&t1, h->events[k], h->events[k + 1]));
+        HIP_TRY(h, hipEventElapsedTime(&t2, h->events[k + 1], h->events[k + 2]));
+        a += t1;
+        b += t2;
+    }
+    if (psi_ms) *psi_ms = a;
+    if (fused_ms) *fused_ms = b;
+    if (steps) *steps = h->timed_steps;
+    h->events_used = 0;
+    h->timed_steps = 0;
+    return LBM_OK;
+}
+
+int lbm_eos_critical(const lbm_eos *eos, double *rho_c, double *T_c, double *p_c) {
+    if (!eos || !(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
+    critical(eos->a, eos->b, eos->R, rho_c, T_c, p_c);
+    return LBM_OK;
+}
+
+int lbm_eos_maxwell(const lbm_eos *eos, double *rho_g, double *rho_l) {
+    if (!eos || !rho_g || !rho_l || !(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
+    if (!(eos->T_over_Tc > 0 && eos->T_over_Tc < 1)) return LBM_EINVAL;
+    return maxwell(*eos, rho_g, rho_l);
+}
+
+const char *lbm_strerror(int code) {
+    switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_EUNSTABLE: return "unstable state";
+    case LBM_ENOTCONVERGED: return "not converged";
+    case LBM_ESTATE: return "call out of order";
+    default: return "unknown error";
+    }
+}
+
+const char *lbm_last_error(const lbm_t *h) { return h ? h->err.c_str() : ""; }
+
+int lbm_copy_f32(float *dst, const float *src, size_t n, void *stream) {
+    if (!dst || !src) return LBM_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) & 15) return LBM_EINVAL;
+    return pplbm::launch_copy(dst, src, n, (hipStream_t)stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Internal interface between the C ABI runtime (lbm_api.cpp) and the gfx950 kernels
+// (lbm_kernels.hip).  Not installed; the public interface is include/pplbm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace pplbm {
+
+enum Scheme { EDM = 0, GUO = 1, GUO_LI = 2 };
+enum Coll { BGK = 0, MRT = 1 };
+
+// Everything a step needs, in FP64; the launchers convert to the kernels' arithmetic type.
+struct Physics {
+    int nx, ny;
+    size_t pitch;   // floats per row
+    size_t plane;   // floats per population plane
+    double b_quarter;   // b / 4                     (Eq. 29)
+    double RT;          // R * T                     (Eq. 29)
+    double a;           // attraction constant       (Eq. 29)
+    double K;           // EOS rescale               (Eq. 30)
+    double G;           // interaction strength      (Eq. 4-7), < 0
+    double A;           // hybrid weight             (Eq. 6)
+    double sigma;       // Li's constant             (Eq. 31)
+    double tau;         // relaxation time           (Eq. 1)
+    double s[9];        // MRT rates, moment order (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
+    int scheme, coll;
+};
+
+// Density / psi pass (Eq. 3, Eq. 29-30, Eq. 7): psi[y * pitch + x] from f.
+hipError_t launch_psi(const Physics &p, bool fp64, const float *f, float *psi,
+                      hipStream_t stream);
+
+// Fused pass: force (Eq. 6) + forcing scheme + BGK/MRT collision + push streaming (Eq. 36).
+hipError_t launch_fused(const Physics &p, bool fp64, int tx, int ty, const float *fin,
+                        const float *psi, float *fout, hipStream_t stream);
+
+// f = f^eq(rho0, u0) (Eq. 2); rho0 [ny*nx], u0 [ny*nx*2] or null, device FP64.
+hipError_t launch_init(const Physics &p, const double *rho0, const double *u0, float *f,
+                       hipStream_t stream);
+
+// rho and v = u + F/(2 rho) into device FP64 arrays (compact, x fastest); needs a psi pass
+// on the same f first.
+hipError_t launch_macro(const Physics &p, const float *f, const float *psi, double *rho,
+                        double *u, hipStream_t stream);
+
+// Deterministic FP64 reduction of the observables.  partial must hold
+// stats_partial_count(p) * kStatsFields doubles, out kStatsOut doubles.  vprev (2 floats per
+// node, pitch layout) may be null; when given, dv is measured against it and it is updated.
+constexpr int kStatsFields = 6;  // sum rho, min rho, max rho, max |v|, max |dv|, nonfinite
+constexpr int kStatsOut = 8;     // the six above + rho at probe a, rho at probe b
+size_t stats_partial_count(const Physics &p);
+hipError_t launch_stats(const Physics &p, const float *f, const float *psi, float *vprev,
+                        double *partial, double *out, int xa, int ya, int xb, int yb,
+                        hipStream_t stream);
+
+hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t stream);
+
+}  // namespace pplbm

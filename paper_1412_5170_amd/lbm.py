@@ -1,0 +1,217 @@
+"""ctypes binding of libpplbm.so (include/pplbm.h), same function names as the C ABI.
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+torch provides device memory and the stream (``Lattice``); nothing falls back to a CPU path
+-- if the library is missing, importing this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpplbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ENOTCONVERGED, LBM_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+LBM_EOS_CARNAHAN_STARLING = 0
+LBM_FORCE_EDM, LBM_FORCE_GUO, LBM_FORCE_GUO_LI = 0, 1, 2
+LBM_COLL_BGK, LBM_COLL_MRT = 0, 1
+LBM_PREC_F32, LBM_PREC_F64 = 0, 1
+
+SCHEMES = {"EDM": LBM_FORCE_EDM, "GUO": LBM_FORCE_GUO, "GUO_LI": LBM_FORCE_GUO_LI}
+COLLISIONS = {"BGK": LBM_COLL_BGK, "MRT": LBM_COLL_MRT}
+
+
+class lbm_eos(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("R", ctypes.c_double), ("T_over_Tc", ctypes.c_double), ("K", ctypes.c_double)]
+
+
+class lbm_force(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("A", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("G", ctypes.c_double)]
+
+
+class lbm_collision(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double),
+                ("s_eps", ctypes.c_double), ("s_j", ctypes.c_double), ("s_q", ctypes.c_double)]
+
+
+class lbm_stats_t(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("rho_probe_a", ctypes.c_double),
+                ("rho_probe_b", ctypes.c_double), ("ratio", ctypes.c_double),
+                ("us_max", ctypes.c_double), ("dv_max", ctypes.c_double),
+                ("step", ctypes.c_longlong), ("nonfinite", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_5170_amd.build` "
+                      "(there is no CPU fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_SIG = {
+    "lbm_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(lbm_eos),
+                                  ctypes.POINTER(lbm_force), ctypes.POINTER(lbm_collision),
+                                  ctypes.c_double, ctypes.POINTER(_P)]),
+    "lbm_destroy": (None, [_P]),
+    "lbm_layout": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_size_t)] * 4),
+    "lbm_attach": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "lbm_set_stream": (ctypes.c_int, [_P, _P]),
+    "lbm_set_precision": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_set_tile": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "lbm_set_probes": (ctypes.c_int, [_P] + [ctypes.c_int] * 4),
+    "lbm_init": (ctypes.c_int, [_P, _D, _D]),
+    "lbm_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_read": (ctypes.c_int, [_P, _D, _D]),
+    "lbm_populations": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_set_populations": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
+    "lbm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_timing": (ctypes.c_int, [_P, _D, _D, ctypes.POINTER(ctypes.c_longlong)]),
+    "lbm_eos_critical": (ctypes.c_int, [ctypes.POINTER(lbm_eos), _D, _D, _D]),
+    "lbm_eos_maxwell": (ctypes.c_int, [ctypes.POINTER(lbm_eos), _D, _D]),
+    "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lbm_last_error": (ctypes.c_char_p, [_P]),
+    "lbm_copy_f32": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__(f"{lbm_strerror(code).decode()} ({code}): {msg}")
+
+
+def check(code, handle=None):
+    if code != LBM_OK:
+        msg = lbm_last_error(handle).decode() if handle else ""
+        raise LBMError(code, msg)
+    return code
+
+
+def _dptr(a):
+    if a is None:
+        return ctypes.cast(None, _D)
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def make_eos(T_over_Tc, K=1.0, a=1.0, b=4.0, R=1.0):
+    return lbm_eos(LBM_EOS_CARNAHAN_STARLING, a, b, R, T_over_Tc, K)
+
+
+def make_force(scheme="GUO", A=0.0, sigma=0.0, G=-1.0):
+    return lbm_force(SCHEMES[scheme] if isinstance(scheme, str) else scheme, A, sigma, G)
+
+
+def make_collision(kind="BGK", s=(1.0, 1.1, 1.1, 1.0, 1.1)):
+    """s = (s_rho, s_e, s_eps, s_j, s_q); s_nu = 1/tau is implied (Eq. 35)."""
+    return lbm_collision(COLLISIONS[kind] if isinstance(kind, str) else kind, *s)
+
+
+def eos_critical(eos: lbm_eos):
+    rc, Tc, pc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(lbm_eos_critical(ctypes.byref(eos), ctypes.byref(rc), ctypes.byref(Tc), ctypes.byref(pc)))
+    return rc.value, Tc.value, pc.value
+
+
+def eos_maxwell(eos: lbm_eos):
+    g, l = ctypes.c_double(), ctypes.c_double()
+    check(lbm_eos_maxwell(ctypes.byref(eos), ctypes.byref(g), ctypes.byref(l)))
+    return g.value, l.value
+
+
+class Lattice:
+    """One periodic lattice whose buffers and stream come from torch (device memory only)."""
+
+    def __init__(self, nx, ny, eos, force, collision, tau, precision=LBM_PREC_F64,
+                 tile=None, device="cuda:0", stream=None):
+        import torch  # torch supplies device memory and the stream
+        self.nx, self.ny = nx, ny
+        h = _P()
+        check(lbm_create(nx, ny, ctypes.byref(eos), ctypes.byref(force), ctypes.byref(collision),
+                         float(tau), ctypes.byref(h)))
+        self.h = h
+        pitch, plane, fb, pb = (ctypes.c_size_t() for _ in range(4))
+        check(lbm_layout(h, ctypes.byref(pitch), ctypes.byref(plane), ctypes.byref(fb),
+                         ctypes.byref(pb)), h)
+        self.pitch, self.plane = pitch.value, plane.value
+        dev = torch.device(device)
+        self.f_a = torch.zeros(fb.value // 4, dtype=torch.float32, device=dev)
+        self.f_b = torch.zeros(fb.value // 4, dtype=torch.float32, device=dev)
+        self.psi = torch.zeros(pb.value // 4, dtype=torch.float32, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        check(lbm_attach(h, self.f_a.data_ptr(), self.f_b.data_ptr(), self.psi.data_ptr(),
+                         self.stream.cuda_stream), h)
+        check(lbm_set_precision(h, precision), h)
+        if tile is not None:
+            check(lbm_set_tile(h, *tile), h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lbm_destroy(h)
+            self.h = None
+
+    def init(self, rho0, u0=None):
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert rho0.shape == (self.ny, self.nx)
+        u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+        check(lbm_init(self.h, _dptr(rho0), _dptr(u0)), self.h)
+
+    def step(self, n=1):
+        check(lbm_step(self.h, int(n)), self.h)
+
+    def read(self):
+        rho = np.empty((self.ny, self.nx))
+        u = np.empty((self.ny, self.nx, 2))
+        check(lbm_read(self.h, _dptr(rho), _dptr(u)), self.h)
+        return rho, u
+
+    def populations(self):
+        f = np.empty((9, self.ny, self.nx), dtype=np.float32)
+        check(lbm_populations(self.h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.h)
+        return f
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        assert f.shape == (9, self.ny, self.nx)
+        check(lbm_set_populations(self.h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.h)
+
+    def stats(self, track_dv=False, allow_unstable=False):
+        s = lbm_stats_t()
+        rc = lbm_stats(self.h, int(track_dv), ctypes.byref(s))
+        if rc != LBM_OK and not (allow_unstable and rc == LBM_EUNSTABLE):
+            check(rc, self.h)
+        return s.as_dict()
+
+    def set_probes(self, xa, ya, xb, yb):
+        check(lbm_set_probes(self.h, xa, ya, xb, yb), self.h)
+
+    def set_tile(self, tx, ty):
+        check(lbm_set_tile(self.h, tx, ty), self.h)
+
+    def set_precision(self, precision):
+        check(lbm_set_precision(self.h, precision), self.h)
+
+    def timing_enable(self, on=True):
+        check(lbm_timing_enable(self.h, int(on)), self.h)
+
+    def timing(self):
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+        check(lbm_timing(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), self.h)
+        return a.value, b.value, n.value

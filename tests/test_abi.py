@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports every function include/pplbm.h declares, and its host-only
+entry points (EOS helpers, validation, error text) work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1412_5170_amd import lbm
+    return lbm
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_critical_point_matches_oracle(L, thermo):
+    rc, Tc, pc = L.eos_critical(L.make_eos(0.5))
+    orc, oTc, opc = thermo.critical_point()
+    assert Tc == pytest.approx(oTc, rel=1e-13)
+    assert rc == pytest.approx(orc, rel=1e-9)      # flat optimum: rho_c is less sharply defined
+    assert pc == pytest.approx(opc, rel=1e-12)
+    # other constants scale as Tc = 0.37731 a / (b R)
+    _, Tc2, _ = L.eos_critical(L.make_eos(0.5, a=2.0, b=3.0, R=0.5))
+    assert Tc2 == pytest.approx(Tc * (2.0 / 1.0) * (4.0 / 3.0) / 0.5, rel=1e-13)
+
+
+@pytest.mark.parametrize("ttc", [0.5, 0.6, 0.8, 0.9])
+def test_maxwell_matches_oracle(L, thermo, ttc):
+    g, l = L.eos_maxwell(L.make_eos(ttc, K=1 / 49))
+    og, ol, _ = thermo.maxwell(ttc)
+    assert g == pytest.approx(og, rel=1e-9) and l == pytest.approx(ol, rel=1e-11)
+
+
+def _create(L, nx=8, ny=8, eos=None, force=None, coll=None, tau=1.0):
+    h = ctypes.c_void_p()
+    rc = L.lbm_create(nx, ny, ctypes.byref(eos or L.make_eos(0.6)),
+                      ctypes.byref(force or L.make_force("GUO")),
+                      ctypes.byref(coll or L.make_collision("BGK")), tau, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validates(L):
+    assert _create(L, tau=0.5)[0] == L.LBM_EINVAL
+    assert _create(L, nx=0)[0] == L.LBM_EINVAL
+    assert _create(L, force=L.make_force("GUO", G=1.0))[0] == L.LBM_EINVAL
+    assert _create(L, force=L.make_force("EDM"), coll=L.make_collision("MRT"))[0] == L.LBM_EINVAL
+    assert _create(L, coll=L.make_collision("MRT", s=(1.0, 2.5, 1.1, 1.0, 1.1)))[0] == L.LBM_EINVAL
+    assert _create(L, eos=L.make_eos(0.6, K=0.0))[0] == L.LBM_EINVAL
+    rc, h = _create(L, nx=3, ny=5)
+    assert rc == L.LBM_OK and h
+    pitch, plane, fb, pb = (ctypes.c_size_t() for _ in range(4))
+    assert L.lbm_layout(h, *(ctypes.byref(v) for v in (pitch, plane, fb, pb))) == 0
+    assert pitch.value == 64 and plane.value == 64 * 5 and fb.value == 9 * 64 * 5 * 4
+    assert L.lbm_set_tile(h, 48, 4) == L.LBM_EINVAL and L.lbm_set_tile(h, 128, 8) == 0
+    assert L.lbm_set_probes(h, 3, 0, 0, 0) == L.LBM_EINVAL
+    assert L.lbm_set_precision(h, 7) == L.LBM_EINVAL
+    # stepping before init is an ordering error, reported without touching the GPU
+    assert L.lbm_step(h, 1) == L.LBM_ESTATE
+    assert b"init" in L.lbm_last_error(h)
+    L.lbm_destroy(h)
+    assert L.lbm_strerror(L.LBM_EUNSTABLE) == b"unstable state"
+
+
+def test_binding_has_no_cpu_path():
+    """The product path has no CPU fallback: the binding module only loads the HIP library."""
+    src = open(os.path.join(ROOT, "paper_1412_5170_amd", "lbm.py")).read()
+    assert "oracle" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_1412_5170_amd")):
+        if f.endswith(".py"):
+            assert "import oracle" not in open(os.path.join(ROOT, "paper_1412_5170_amd", f)).read()
