@@ -16,11 +16,13 @@
  *     the ABI.  lbm_last_error() gives the text of the last failure on a handle.
  *   - Host arrays belong to the caller, are FP64, row-major with x fastest: index y*nx + x.
  *     A velocity array holds the pair (u_x, u_y) per node: index 2*(y*nx + x) + {0, 1}.
- *   - Device state: populations are FP32, nine SoA planes per buffer, plane a at
- *     a * plane_floats, node (x, y) at y * pitch + x inside a plane.  Two population
- *     buffers (read and write side of the step) and one psi plane (ny * pitch floats).
- *     They belong to the handle unless lbm_attach supplied them; attached memory must
- *     outlive the handle.
+ *   - Device state: FP32 populations, population a of node (x, y) at
+ *     y * row_stride + a * velocity_stride + x (lbm_strides): the nine rows of each y next to
+ *     each other (LBM_LAYOUT_ROWS, the default: row_stride = 9 * pitch,
+ *     velocity_stride = pitch) or nine planes one after the other (LBM_LAYOUT_PLANES:
+ *     row_stride = pitch, velocity_stride = pitch * ny).  Two population buffers (read and write side of the step)
+ *     and one psi plane (ny * pitch floats, node at y * pitch + x).  They belong to the
+ *     handle unless lbm_attach supplied them; attached memory must outlive the handle.
  *   - Ordering of the nine velocities: e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0),
  *     e_4 = (0,-1), e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1).
  *   - lbm_step and lbm_init are asynchronous on the handle's stream; lbm_read, lbm_stats and
@@ -50,7 +52,9 @@ enum { LBM_EOS_CARNAHAN_STARLING = 0 };
 enum { LBM_FORCE_EDM = 0, LBM_FORCE_GUO = 1, LBM_FORCE_GUO_LI = 2 };
 enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 /* Arithmetic precision of the kernels; the populations are stored in FP32 either way. */
-enum { LBM_PREC_F32 = 0, LBM_PREC_F64 = 1 };
+enum { LBM_PREC_F32 = 0, LBM_PREC_F64 = 1, LBM_PREC_MIXED = 2 };
+/* Population layout in device memory (see lbm_strides). */
+enum { LBM_LAYOUT_PLANES = 0, LBM_LAYOUT_ROWS = 1 };
 
 /* Equation of state, Eq. 29-30: p = K (rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3 - a rho^2),
  * eta = b rho / 4.  T is given relative to the exact critical temperature of Eq. 29
@@ -124,14 +128,45 @@ int lbm_attach(lbm_t *h, void *f_a, void *f_b, void *psi, void *stream);
 /* Select the stream later calls are issued on (hipStream_t, NULL = default stream). */
 int lbm_set_stream(lbm_t *h, void *stream);
 
-/* Arithmetic precision of the kernels (LBM_PREC_F32 or LBM_PREC_F64, the default).  The
- * populations stay FP32 in memory either way, so the HBM traffic is the same; FP64 arithmetic
- * keeps the FP32-stored state within 1e-5 of an FP64 run after 100 steps, FP32 arithmetic
- * roughly doubles that error. */
+/* Arithmetic precision of the kernels.  The populations stay FP32 in memory either way, so
+ * the memory traffic is the same.
+ *   LBM_PREC_MIXED (default): FP32 arithmetic except the operations whose cancellation sets
+ *     the accuracy of the FP32 state -- the density and momentum sums, the EOS and psi, the
+ *     interaction force, u and v (u and F/(2 rho) nearly cancel in the light phase),
+ *     w rho - f in the relaxation and the mass closure -- which run in FP64.
+ *   LBM_PREC_F64: FP64 throughout.   LBM_PREC_F32: FP32 throughout (about twice the error).
+ * MIXED and F64 keep the state within 1e-5 of an FP64 run after 100 steps. */
 int lbm_set_precision(lbm_t *h, int precision);
 
-/* Tile of the fused pass: tx x ty threads per workgroup (tx a multiple of 64, tx * ty <= 1024).
- * Results do not depend on the tile. */
+/* Population layout (LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS); only before lbm_init or
+ * lbm_set_populations.  Results do not depend on the layout. */
+int lbm_set_layout(lbm_t *h, int layout);
+
+/* Strides (in floats) of the population buffers: node (x, y), velocity a at
+ * y * row_stride + a * velocity_stride + x. */
+int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
+
+/* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
+ * the sweep with tx <= 256, ty <= 32 shrunk until the launch has ~1024 workgroups, flags
+ * LBM_LAUNCH_XCD_ORDER | LBM_LAUNCH_SHALLOW.
+ *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
+ *     reads it; (tx, ty) = threads per workgroup of the fused pass (tx a multiple of 64,
+ *     tx * ty <= 1024).  116 bytes of memory traffic per node and step.
+ *   LBM_KERNEL_SWEEP: one kernel per step; a workgroup of tx threads (multiple of 64, <= 512)
+ *     sweeps a strip of tx columns over segments of ty rows, computing psi from the
+ *     populations as it loads them, so each population is read once: 72 bytes per node and
+ *     step plus the strip and segment edges.
+ * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
+ *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
+ *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */
+enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1 };
+#define LBM_LAUNCH_NONTEMPORAL 1
+#define LBM_LAUNCH_XCD_ORDER 2
+#define LBM_LAUNCH_SHALLOW 4
+int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags);
+int lbm_get_launch(const lbm_t *h, int *kernel, int *tx, int *ty, int *flags);
+
+/* Shorthand for lbm_set_launch(h, LBM_KERNEL_TWO_PASS, tx, ty, current flags). */
 int lbm_set_tile(lbm_t *h, int tx, int ty);
 
 /* Probe nodes reported by lbm_stats (defaults: a = (nx/2, ny/2), b = (0, 0)). */

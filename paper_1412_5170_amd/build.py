@@ -14,6 +14,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # Packed FP32 instructions stay off: scalar/float2 code only.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FMA contraction only inside one statement, so every kernel that inlines the same
+    # per-node code rounds it the same way (bitwise-equal results across kernel shapes).
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -27,8 +27,9 @@ struct lbm {
     bool owned = false;
     int cur = 0;  // index of the buffer holding the current populations
     hipStream_t stream = nullptr;
-    bool fp64 = true;  // FP64 arithmetic, FP32 storage (see lbm_set_precision)
-    int tx = 64, ty = 4;
+    int prec = pplbm::kPrecMixed;  // arithmetic precision (see lbm_set_precision)
+    int layout = LBM_LAYOUT_ROWS;
+    pplbm::Launch launch;
     int xa = 0, ya = 0, xb = 0, yb = 0;
     long long step = 0;
     bool initialised = false;
@@ -158,6 +159,24 @@ int maxwell(const lbm_eos &e, double *rho_g, double *rho_l) {
     return LBM_OK;
 }
 
+// One-pass sweep with strips as wide as 256 columns and segments as tall as 32 rows, narrowed
+// and shortened (down to 64 x 8) until the launch has about 1024 workgroups to spread over the
+// 256 compute units.  lbm_set_launch or an autotuned choice replaces it.
+pplbm::Launch default_launch(int nx, int ny) {
+    pplbm::Launch L;
+    L.kernel = pplbm::kKernelSweep;
+    L.flags = pplbm::kFlagXCD | pplbm::kFlagShallow;
+    L.tx = 256;
+    L.ty = 32;
+    auto groups = [&]() { return (double)((nx + L.tx - 1) / L.tx) * ((ny + L.ty - 1) / L.ty); };
+    while (groups() < 1024 && (L.tx > 64 || L.ty > 8)) {
+        if (L.tx > 64 && (L.tx >= 2 * 64 && nx <= L.tx * 4)) L.tx /= 2;
+        else if (L.ty > 8) L.ty /= 2;
+        else L.tx /= 2;
+    }
+    return L;
+}
+
 int validate(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
              const lbm_collision *coll, double tau, std::string *why) {
     auto bad = [&](const char *m) { *why = m; return LBM_EINVAL; };
@@ -252,6 +271,8 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     p.ny = ny;
     p.pitch = ((size_t)nx + 63) / 64 * 64;
     p.plane = p.pitch * (size_t)ny;
+    p.frow = 9 * p.pitch;  // LBM_LAYOUT_ROWS
+    p.fq = p.pitch;
     p.b_quarter = eos->b / 4.0;
     p.RT = eos->R * h->T;
     p.a = eos->a;
@@ -272,6 +293,7 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     }
     h->xa = nx / 2;
     h->ya = ny / 2;
+    h->launch = default_launch(nx, ny);
     *out = h;
     return LBM_OK;
 }
@@ -321,18 +343,61 @@ int lbm_set_stream(lbm_t *h, void *stream) {
 
 int lbm_set_precision(lbm_t *h, int precision) {
     if (!h) return LBM_EINVAL;
-    if (precision != LBM_PREC_F32 && precision != LBM_PREC_F64)
-        return fail(h, LBM_EINVAL, "precision must be LBM_PREC_F32 or LBM_PREC_F64");
-    h->fp64 = precision == LBM_PREC_F64;
+    if (precision != LBM_PREC_F32 && precision != LBM_PREC_F64 && precision != LBM_PREC_MIXED)
+        return fail(h, LBM_EINVAL, "precision must be LBM_PREC_F32, LBM_PREC_F64 or LBM_PREC_MIXED");
+    h->prec = precision;
+    return LBM_OK;
+}
+
+int lbm_set_layout(lbm_t *h, int layout) {
+    if (!h) return LBM_EINVAL;
+    if (layout != LBM_LAYOUT_PLANES && layout != LBM_LAYOUT_ROWS)
+        return fail(h, LBM_EINVAL, "layout must be LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS");
+    if (h->initialised) return fail(h, LBM_ESTATE, "the layout is fixed once the lattice is initialised");
+    h->layout = layout;
+    h->p.frow = layout == LBM_LAYOUT_ROWS ? 9 * h->p.pitch : h->p.pitch;
+    h->p.fq = layout == LBM_LAYOUT_ROWS ? h->p.pitch : h->p.plane;
+    return LBM_OK;
+}
+
+int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride) {
+    if (!h) return LBM_EINVAL;
+    if (row_stride) *row_stride = h->p.frow;
+    if (velocity_stride) *velocity_stride = h->p.fq;
     return LBM_OK;
 }
 
 int lbm_set_tile(lbm_t *h, int tx, int ty) {
     if (!h) return LBM_EINVAL;
-    if (tx < 64 || tx % 64 || ty < 1 || tx * ty > 1024)
-        return fail(h, LBM_EINVAL, "tile: tx a multiple of 64, ty >= 1, tx * ty <= 1024");
-    h->tx = tx;
-    h->ty = ty;
+    return lbm_set_launch(h, LBM_KERNEL_TWO_PASS, tx, ty, h->launch.flags);
+}
+
+int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags) {
+    if (!h) return LBM_EINVAL;
+    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_XCD_ORDER | LBM_LAUNCH_SHALLOW))
+        return fail(h, LBM_EINVAL, "unknown launch flags");
+    if (kernel == LBM_KERNEL_TWO_PASS) {
+        if (tx < 64 || tx % 64 || ty < 1 || tx * ty > 1024)
+            return fail(h, LBM_EINVAL, "two-pass tile: tx a multiple of 64, ty >= 1, tx * ty <= 1024");
+    } else if (kernel == LBM_KERNEL_SWEEP) {
+        if (tx < 64 || tx % 64 || tx > 512 || ty < 1)
+            return fail(h, LBM_EINVAL, "sweep: tx a multiple of 64 up to 512, ty >= 1 rows");
+    } else {
+        return fail(h, LBM_EINVAL, "unknown kernel");
+    }
+    h->launch.kernel = kernel;
+    h->launch.tx = tx;
+    h->launch.ty = ty;
+    h->launch.flags = flags;
+    return LBM_OK;
+}
+
+int lbm_get_launch(const lbm_t *h, int *kernel, int *tx, int *ty, int *flags) {
+    if (!h) return LBM_EINVAL;
+    if (kernel) *kernel = h->launch.kernel;
+    if (tx) *tx = h->launch.tx;
+    if (ty) *ty = h->launch.ty;
+    if (flags) *flags = h->launch.flags;
     return LBM_OK;
 }
 
@@ -397,9 +462,14 @@ int lbm_step(lbm_t *h, int n) {
             h->events_used += 3;
             HIP_TRY(h, hipEventRecord(ev[0], h->stream));
         }
-        HIP_TRY(h, pplbm::launch_psi(h->p, h->fp64, fc, h->psi, h->stream));
-        if (ev) HIP_TRY(h, hipEventRecord(ev[1], h->stream));
-        HIP_TRY(h, pplbm::launch_fused(h->p, h->fp64, h->tx, h->ty, fc, h->psi, fn, h->stream));
+        if (h->launch.kernel == pplbm::kKernelSweep) {
+            if (ev) HIP_TRY(h, hipEventRecord(ev[1], h->stream));
+            HIP_TRY(h, pplbm::launch_sweep(h->p, h->prec, h->launch, fc, fn, h->stream));
+        } else {
+            HIP_TRY(h, pplbm::launch_psi(h->p, h->prec, h->launch.flags, fc, h->psi, h->stream));
+            if (ev) HIP_TRY(h, hipEventRecord(ev[1], h->stream));
+            HIP_TRY(h, pplbm::launch_fused(h->p, h->prec, h->launch, fc, h->psi, fn, h->stream));
+        }
         if (ev) {
             HIP_TRY(h, hipEventRecord(ev[2], h->stream));
             ++h->timed_steps;
@@ -420,7 +490,7 @@ int lbm_read(lbm_t *h, double *rho, double *u) {
         return fail(h, LBM_ENOMEM, "staging allocation failed");
     }
     float *fc = h->f[h->cur];
-    hipError_t e = pplbm::launch_psi(h->p, true, fc, h->psi, h->stream);
+    hipError_t e = pplbm::launch_psi(h->p, pplbm::kPrecF64, 0, fc, h->psi, h->stream);
     if (e == hipSuccess) e = pplbm::launch_macro(h->p, fc, h->psi, d, d + N, h->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + N, 2 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -437,7 +507,7 @@ int lbm_populations(lbm_t *h, float *f) {
     const float *src = h->f[h->cur];
     for (int q = 0; q < 9; ++q)
         HIP_TRY(h, hipMemcpy2DAsync(f + (size_t)q * p.nx * p.ny, p.nx * sizeof(float),
-                                    src + q * p.plane, p.pitch * sizeof(float), p.nx * sizeof(float),
+                                    src + q * p.fq, p.frow * sizeof(float), p.nx * sizeof(float),
                                     p.ny, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -450,7 +520,7 @@ int lbm_set_populations(lbm_t *h, const float *f) {
     const Physics &p = h->p;
     float *dst = h->f[h->cur];
     for (int q = 0; q < 9; ++q)
-        HIP_TRY(h, hipMemcpy2DAsync(dst + q * p.plane, p.pitch * sizeof(float),
+        HIP_TRY(h, hipMemcpy2DAsync(dst + q * p.fq, p.frow * sizeof(float),
                                     f + (size_t)q * p.nx * p.ny, p.nx * sizeof(float),
                                     p.nx * sizeof(float), p.ny, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -473,7 +543,7 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out) {
         h->vprev_valid = false;
     }
     float *fc = h->f[h->cur];
-    HIP_TRY(h, pplbm::launch_psi(h->p, true, fc, h->psi, h->stream));
+    HIP_TRY(h, pplbm::launch_psi(h->p, pplbm::kPrecF64, 0, fc, h->psi, h->stream));
     HIP_TRY(h, pplbm::launch_stats(h->p, fc, h->psi, track_dv ? h->vprev : nullptr, h->stats_partial,
                                    h->stats_out, h->xa, h->ya, h->xb, h->yb, h->stream));
     double r[pplbm::kStatsOut];

@@ -14,8 +14,10 @@ enum Coll { BGK = 0, MRT = 1 };
 // Everything a step needs, in FP64; the launchers convert to the kernels' arithmetic type.
 struct Physics {
     int nx, ny;
-    size_t pitch;   // floats per row
-    size_t plane;   // floats per population plane
+    size_t pitch;   // floats per row of the psi plane (multiple of 64, >= nx)
+    size_t plane;   // floats per population plane (pitch * ny)
+    size_t frow;    // population row stride: pitch (planes layout) or 9 * pitch (rows layout)
+    size_t fq;      // population velocity stride: plane (planes layout) or pitch (rows layout)
     double b_quarter;   // b / 4                     (Eq. 29)
     double RT;          // R * T                     (Eq. 29)
     double a;           // attraction constant       (Eq. 29)
@@ -28,13 +30,31 @@ struct Physics {
     int scheme, coll;
 };
 
+enum { kPrecF32 = 0, kPrecF64 = 1, kPrecMixed = 2 };
+constexpr int kFlagNT = 1;   // non-temporal stores of the new populations
+constexpr int kFlagXCD = 2;  // XCD-aware order of the tiles
+constexpr int kFlagShallow = 4;  // sweep: prefetch one row ahead instead of two
+enum { kKernelTwoPass = 0, kKernelSweep = 1 };
+
+// Shape of the step launch.  Two-pass: (tx, ty) is the fused pass's tile.  Sweep: tx columns
+// per workgroup, ty rows per segment.
+struct Launch {
+    int kernel = kKernelTwoPass;
+    int tx = 64, ty = 4;
+    int flags = 0;
+};
+
 // Density / psi pass (Eq. 3, Eq. 29-30, Eq. 7): psi[y * pitch + x] from f.
-hipError_t launch_psi(const Physics &p, bool fp64, const float *f, float *psi,
+hipError_t launch_psi(const Physics &p, int prec, int flags, const float *f, float *psi,
                       hipStream_t stream);
 
 // Fused pass: force (Eq. 6) + forcing scheme + BGK/MRT collision + push streaming (Eq. 36).
-hipError_t launch_fused(const Physics &p, bool fp64, int tx, int ty, const float *fin,
+hipError_t launch_fused(const Physics &p, int prec, const Launch &L, const float *fin,
                         const float *psi, float *fout, hipStream_t stream);
+
+// Whole step in one pass (psi recomputed from f along a sweep): fin -> fout.
+hipError_t launch_sweep(const Physics &p, int prec, const Launch &L, const float *fin,
+                        float *fout, hipStream_t stream);
 
 // f = f^eq(rho0, u0) (Eq. 2); rho0 [ny*nx], u0 [ny*nx*2] or null, device FP64.
 hipError_t launch_init(const Physics &p, const double *rho0, const double *u0, float *f,

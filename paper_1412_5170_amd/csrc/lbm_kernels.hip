@@ -1,16 +1,26 @@
 // gfx950 kernels of the pseudo-potential D2Q9 lattice Boltzmann step (arXiv:1412.5170).
 //
-// State: FP32 populations in nine SoA planes (plane q at q * plane, node at y * pitch + x),
-// double-buffered; one FP32 psi plane.  A time step is two launches:
-//   psi_kernel    rho = sum_q f_q (Eq. 3), psi from the K-rescaled Carnahan-Starling EOS
-//                 (Eq. 29-30) through p0 = rho/3 + G psi^2/2 (Eq. 7).  Reads 36 B, writes 4 B
-//                 per node.
-//   fused_kernel  stages the psi tile plus a one-node halo in LDS, forms the hybrid
-//                 interaction force (Eq. 6; Eq. 4 for A = 0), the moments and velocities
-//                 (Sec. 3.2), the forcing scheme (EDM Eq. 22, Guo Eq. 23, Guo + Li Eq. 31),
-//                 the BGK (Eq. 1) or MRT (Eq. 34-35) collision, and pushes f* to the
-//                 neighbours (Eq. 36, periodic).  Reads 36 B + psi, writes 36 B per node.
-// The arithmetic type R is float or double; storage is FP32 either way.
+// State: FP32 populations, population q of node (x, y) at y * frow + q * fq + x (nine planes
+// either one after the other, fq = pitch * ny, frow = pitch, or interleaved by rows,
+// fq = pitch, frow = 9 * pitch), double-buffered; one FP32 psi plane (y * pitch + x).
+//
+// A time step is either
+//   psi_kernel + fused_kernel (two passes): the first pass forms rho = sum_q f_q (Eq. 3) and
+//     psi from the K-rescaled Carnahan-Starling EOS (Eq. 29-30) through p0 = rho/3 + G psi^2/2
+//     (Eq. 7) and writes psi; the second stages psi of a tile and its one-node halo in LDS,
+//     forms the interaction force (Eq. 6; Eq. 4 for A = 0), the velocities (Sec. 3.2), the
+//     forcing scheme (EDM Eq. 22, Guo Eq. 23, Guo + Li Eq. 31), the BGK (Eq. 1) or MRT
+//     (Eq. 34-35) collision, and pushes f* to the neighbours (Eq. 36, periodic);
+// or
+//   sweep_kernel (one pass): the same per-node arithmetic, with psi computed from the
+//     populations as each row is loaded and kept in an LDS ring, so each population is read
+//     once per step.
+//
+// Arithmetic: D is the type of every quantity of the size of a population (rho, momentum,
+// the force and the velocities, f^eq - f and its moments, the update, the mass closure, the
+// EOS), whose rounding decides the accuracy of the FP32 state; R is the type of the small
+// relative terms (equilibrium shape, Guo's bracket and source, Li's term).
+// (R, D) = (float, float), (double, double) or (float, double).
 //
 // Velocity order: 0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1),
 // 7 (-1,-1), 8 (1,-1).  All formulas below are unrolled by hand for this order.
@@ -23,8 +33,8 @@
 namespace pplbm {
 namespace {
 
-template <typename R>
-__device__ __forceinline__ R qnan();
+template <typename T>
+__device__ __forceinline__ T qnan();
 template <>
 __device__ __forceinline__ float qnan<float>() { return __builtin_nanf(""); }
 template <>
@@ -36,183 +46,157 @@ __device__ __forceinline__ int wrap_any(int g, int n) {
 }
 
 // rho = sum_q f_q in one fixed order, shared by every kernel that needs it.
-template <typename R>
-__device__ __forceinline__ R density(R f0, R f1, R f2, R f3, R f4, R f5, R f6, R f7, R f8) {
+template <typename T>
+__device__ __forceinline__ T density(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T f7, T f8) {
     return ((f0 + (f1 + f3)) + (f2 + f4)) + ((f5 + f7) + (f6 + f8));
+}
+
+template <typename T>
+__device__ __forceinline__ T density9(const float f[9]) {
+    return density<T>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
 }
 
 // Effective density of Eq. 7 with the rescaled Carnahan-Starling pressure of Eq. 29-30.
 // NaN when the node is outside the EOS (b rho/4 >= 1) or 2 U / G <= 0.
-template <typename R>
-__device__ __forceinline__ R eos_psi(R rho, R bq, R RT, R a, R K, R two_over_G) {
-    const R eta = bq * rho;
-    if (!(eta < R(1)) || !(rho > R(0))) return qnan<R>();
-    const R om = R(1) - eta;
-    const R Z = (R(1) + eta * (R(1) + eta * (R(1) - eta))) / (om * om * om);
-    const R p0 = K * (rho * (RT * Z - a * rho));
-    const R r = two_over_G * (p0 - rho / R(3));
-    return r > R(0) ? sqrt(r) : qnan<R>();
+template <typename T>
+__device__ __forceinline__ T eos_psi(T rho, T bq, T RT, T a, T K, T two_over_G) {
+    const T eta = bq * rho;
+    if (!(eta < T(1)) || !(rho > T(0))) return qnan<T>();
+    const T om = T(1) - eta;
+    const T Z = (T(1) + eta * (T(1) + eta * (T(1) - eta))) / (om * om * om);
+    const T p0 = K * (rho * (RT * Z - a * rho));
+    const T r = two_over_G * (p0 - rho / T(3));
+    return r > T(0) ? sqrt(r) : qnan<T>();
 }
 
 // ---------------------------------------------------------------------------------------
-// Density / psi pass.
+// Constants of a step, converted once on the host.
 // ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(256) psi_kernel(const float *__restrict__ f,
-                                                  float *__restrict__ psi, int nx, int ny,
-                                                  size_t pitch, size_t plane, R bq, R RT, R a,
-                                                  R K, R two_over_G) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    for (int y = blockIdx.y; y < ny; y += gridDim.y) {
-        const size_t i = (size_t)y * pitch + x;
-        const R rho = density<R>(f[i], f[i + plane], f[i + 2 * plane], f[i + 3 * plane],
-                                 f[i + 4 * plane], f[i + 5 * plane], f[i + 6 * plane],
-                                 f[i + 7 * plane], f[i + 8 * plane]);
-        psi[i] = (float)eos_psi<R>(rho, bq, RT, a, K, two_over_G);
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// Fused force + collision + streaming pass.
-// ---------------------------------------------------------------------------------------
-template <typename R>
+template <typename R, typename D>
 struct StepConst {
     int nx, ny;
-    size_t pitch, plane;
-    R gA;     // -G A / 2        coefficient of sum w psi^2 e    (Eq. 6, U = G psi^2 / 2)
-    R gB;     // -G (1 - A)      coefficient of psi(x) sum w psi e
-    R omega;  // 1 / tau
-    R kguo;   // 1 - 1/(2 tau)   (Eq. 23)
+    size_t pitch;      // psi row stride (floats)
+    size_t frow, fq;   // population row and velocity strides (floats)
+    int flags;         // kFlagNT | kFlagXCD
+    D bq, RT, a, K, two_over_G;  // EOS (Eq. 29-30) and Eq. 7
+    D gA;     // -G A / 2        coefficient of sum w psi^2 e    (Eq. 6, U = G psi^2 / 2)
+    D gB;     // -G (1 - A)      coefficient of psi(x) sum w psi e
+    D omega;  // 1 / tau
+    D kguo;   // 1 - 1/(2 tau)   (Eq. 23)
     R li;     // sigma / (tau - 1/2): v' = v + li F / psi^2 (Eq. 31)
     R li2;    // 2 sigma: Li's extra stress X = li2 F F / psi^2 (MRT form)
-    R s[9];   // MRT rates in moment order
-    R hs[9];  // 1 - s/2
+    D s[9];   // MRT rates in moment order
+    D hs[9];  // 1 - s/2
     R lim[9]; // 1 / (1/s_k - 1/2) for the moments that carry Li's stress
+
+    __device__ __forceinline__ float psi_of(const float f[9]) const {
+        return (float)eos_psi<D>(density9<D>(f), bq, RT, a, K, two_over_G);
+    }
 };
 
+// psi of the node and of its eight neighbours.
 template <typename R>
-__device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R fe[9]) {
-    // Eq. 2 with c_s^2 = 1/3: w rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u)
-    const R w0 = R(4) / R(9), w1 = R(1) / R(9), w2 = R(1) / R(36);
+struct Nb {
+    R c, E, W, N, S, NE, NW, SW, SE;
+};
+
+// Equilibrium of Eq. 2 (c_s^2 = 1/3) written as f^eq_q = w_q rho (1 + s_q),
+// s_q = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u; returns s_q.
+template <typename R>
+__device__ __forceinline__ void eq_shape(R ux, R uy, R s[9]) {
     const R usq = R(1.5) * (ux * ux + uy * uy);
-    const R r0 = w0 * rho, r1 = w1 * rho, r2 = w2 * rho;
-    fe[0] = r0 * (R(1) - usq);
-    const R ea[4] = {ux, uy, -ux, -uy};
+    s[0] = -usq;
+    const R e[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const R e = ea[q];
-        fe[1 + q] = r1 * (R(1) + R(3) * e + R(4.5) * e * e - usq);
-    }
-    const R ed[4] = {ux + uy, uy - ux, -ux - uy, ux - uy};
+    for (int q = 0; q < 8; ++q) s[1 + q] = R(3) * e[q] + R(4.5) * e[q] * e[q] - usq;
+}
+
+template <typename T>
+__device__ __forceinline__ T wgt(int q) {
+    return q == 0 ? T(4) / T(9) : (q < 5 ? T(1) / T(9) : T(1) / T(36));
+}
+
+// f^eq_q(rho, u) - f_q in D: the non-equilibrium part can be as large as f itself (in the
+// light phase next to an interface u and v differ by F/(2 rho)), so it is formed in D; only the
+// shape term s_q (relative accuracy suffices) comes from R.
+template <typename R, typename D>
+__device__ __forceinline__ void eq_minus_f(D rho_d, R ux, R uy, const float f[9], D out[9]) {
+    R s[9];
+    eq_shape<R>(ux, uy, s);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const R e = ed[q];
-        fe[5 + q] = r2 * (R(1) + R(3) * e + R(4.5) * e * e - usq);
+    for (int q = 0; q < 9; ++q) {
+        const D wr = wgt<D>(q) * rho_d;
+        out[q] = (wr - (D)f[q]) + wr * (D)s[q];
     }
 }
 
 // Guo's bracket B_q = w_q [3 e.F + 9 (e.F)(e.V) - 3 F.V] (Eq. 23 with c_s^2 = 1/3).
 template <typename R>
 __device__ __forceinline__ void guo_bracket(R Fx, R Fy, R Vx, R Vy, R B[9]) {
-    const R w0 = R(4) / R(9), w1 = R(1) / R(9), w2 = R(1) / R(36);
     const R FV = R(3) * (Fx * Vx + Fy * Vy);
-    B[0] = -w0 * FV;
+    B[0] = -wgt<R>(0) * FV;
     const R eF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
     const R eV[8] = {Vx, Vy, -Vx, -Vy, Vx + Vy, Vy - Vx, -Vx - Vy, Vx - Vy};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const R w = q < 4 ? w1 : w2;
-        B[1 + q] = w * (R(3) * eF[q] + R(9) * eF[q] * eV[q] - FV);
-    }
+    for (int q = 0; q < 8; ++q) B[1 + q] = wgt<R>(1 + q) * (R(3) * eF[q] + R(9) * eF[q] * eV[q] - FV);
 }
 
-template <typename R, int SCHEME, int COLL>
-__global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ fin,
-                                                     const float *__restrict__ psi,
-                                                     float *__restrict__ fout,
-                                                     StepConst<R> c) {
-    extern __shared__ float tile[];
-    const int TX = blockDim.x, TY = blockDim.y;
-    const int W = TX + 2;
-    const int nx = c.nx, ny = c.ny;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-
-    // Stage psi of the tile and its one-node halo (periodic) in LDS.
-    const bool inner = x0 >= 1 && x0 + TX < nx && y0 >= 1 && y0 + TY < ny;
-    for (int ly = ty; ly < TY + 2; ly += TY) {
-        int gy = y0 + ly - 1;
-        if (!inner) gy = wrap_any(gy, ny);
-        const float *row = psi + (size_t)gy * c.pitch;
-        for (int lx = tx; lx < W; lx += TX) {
-            int gx = x0 + lx - 1;
-            if (!inner) gx = wrap_any(gx, nx);
-            tile[ly * W + lx] = row[gx];
-        }
-    }
-    __syncthreads();
-
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= nx || y >= ny) return;
-
-    const size_t pl = c.plane;
-    const size_t i = (size_t)y * c.pitch + x;
-    const R f0 = fin[i], f1 = fin[i + pl], f2 = fin[i + 2 * pl], f3 = fin[i + 3 * pl],
-            f4 = fin[i + 4 * pl], f5 = fin[i + 5 * pl], f6 = fin[i + 6 * pl],
-            f7 = fin[i + 7 * pl], f8 = fin[i + 8 * pl];
-
-    // Interaction force, Eq. 6: sums over the eight links as differences of opposite pairs.
-    const int lc = (ty + 1) * W + tx + 1;
-    const R pc = tile[lc];
-    const R pE = tile[lc + 1], pW = tile[lc - 1], pN = tile[lc + W], pS = tile[lc - W];
-    const R pNE = tile[lc + W + 1], pNW = tile[lc + W - 1], pSW = tile[lc - W - 1],
-            pSE = tile[lc - W + 1];
-    const R third = R(1) / R(3), twelfth = R(1) / R(12);
-    const R dA = pNE - pSW, dB = pSE - pNW;  // diagonal pair differences
-    const R s1x = third * (pE - pW) + twelfth * (dA + dB);
-    const R s1y = third * (pN - pS) + twelfth * (dA - dB);
-    R Fx = c.gB * pc * s1x;
-    R Fy = c.gB * pc * s1y;
-    if (c.gA != R(0)) {
+// One node of the time step once psi is known around it: interaction force (Eq. 6), moments
+// and velocities (Sec. 3.2), forcing scheme and collision.  f holds the post-streaming
+// populations of the node; fs receives the post-collision ones (FP32, ready to store).
+template <typename R, typename D, int SCHEME, int COLL>
+__device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
+                                        const StepConst<R, D> &c, float fs[9]) {
+    // Eq. 6 with w(1) = 1/3, w(2) = 1/12: link sums as differences of opposite pairs.  In D:
+    // in the light phase u and F/(2 rho) nearly cancel in v, so F and u must be accurate.
+    const D third = D(1) / D(3), twelfth = D(1) / D(12);
+    const D pE = p.E, pW = p.W, pN = p.N, pS = p.S, pNE = p.NE, pNW = p.NW, pSW = p.SW,
+            pSE = p.SE;
+    const D dA = pNE - pSW, dB = pSE - pNW;
+    const D s1x = third * (pE - pW) + twelfth * (dA + dB);
+    const D s1y = third * (pN - pS) + twelfth * (dA - dB);
+    D Fxd = c.gB * (D)p.c * s1x;
+    D Fyd = c.gB * (D)p.c * s1y;
+    if (c.gA != D(0)) {
         // sum w psi^2 e with psi_a^2 - psi_b^2 = (psi_a - psi_b)(psi_a + psi_b)
-        const R qA = dA * (pNE + pSW), qB = dB * (pSE + pNW);
-        const R s2x = third * ((pE - pW) * (pE + pW)) + twelfth * (qA + qB);
-        const R s2y = third * ((pN - pS) * (pN + pS)) + twelfth * (qA - qB);
-        Fx += c.gA * s2x;
-        Fy += c.gA * s2y;
+        const D qA = dA * (pNE + pSW), qB = dB * (pSE + pNW);
+        const D s2x = third * ((pE - pW) * (pE + pW)) + twelfth * (qA + qB);
+        const D s2y = third * ((pN - pS) * (pN + pS)) + twelfth * (qA - qB);
+        Fxd += c.gA * s2x;
+        Fyd += c.gA * s2y;
     }
 
-    // Moments (Eq. 3), u = sum f e / rho, v = u + F / (2 rho) (Sec. 3.2).
-    const R rho = density<R>(f0, f1, f2, f3, f4, f5, f6, f7, f8);
-    const R jx = ((f1 - f3) + (f5 - f7)) + (f8 - f6);
-    const R jy = ((f2 - f4) + (f5 - f7)) + (f6 - f8);
-    const R ux = jx / rho, uy = jy / rho;
-    const R vx = ux + Fx / (R(2) * rho), vy = uy + Fy / (R(2) * rho);
+    // Eq. 3, u = sum f e / rho, v = u + F / (2 rho).  Momentum from opposite-pair differences.
+    const D rho_d = density9<D>(f);
+    const D jx = (((D)f[1] - (D)f[3]) + ((D)f[5] - (D)f[7])) + ((D)f[8] - (D)f[6]);
+    const D jy = (((D)f[2] - (D)f[4]) + ((D)f[5] - (D)f[7])) + ((D)f[6] - (D)f[8]);
+    const D uxd = jx / rho_d, uyd = jy / rho_d;
+    const R rho = (R)rho_d;
+    const R ux = (R)uxd, uy = (R)uyd;
+    const R vx = (R)(uxd + Fxd / (D(2) * rho_d)), vy = (R)(uyd + Fyd / (D(2) * rho_d));
+    const R Fx = (R)Fxd, Fy = (R)Fyd;
+    const R pc = p.c;
 
-    const R fin9[9] = {f0, f1, f2, f3, f4, f5, f6, f7, f8};
-    R fs[9];
-    R fe[9];
+    D upd[9];  // f*_q - f_q
     if constexpr (COLL == BGK) {
+        D neq[9];
         if constexpr (SCHEME == EDM) {
             // Eq. 22 with f^eq(rho, u + D) - f^eq(rho, u) written out exactly:
             // w rho [3 e.D + 9/2 (e.D)(e.(2u + D)) - 3/2 D.(2u + D)],  D = F / rho.
-            equilibrium<R>(rho, ux, uy, fe);
+            eq_minus_f<R, D>(rho_d, ux, uy, f, neq);
             const R Dx = Fx / rho, Dy = Fy / rho;
             const R Sx = R(2) * ux + Dx, Sy = R(2) * uy + Dy;
             const R DS = R(1.5) * (Dx * Sx + Dy * Sy);
             const R eD[9] = {R(0), Dx, Dy, -Dx, -Dy, Dx + Dy, Dy - Dx, -Dx - Dy, Dx - Dy};
             const R eS[9] = {R(0), Sx, Sy, -Sx, -Sy, Sx + Sy, Sy - Sx, -Sx - Sy, Sx - Sy};
-            const R wr[3] = {R(4) / R(9) * rho, R(1) / R(9) * rho, R(1) / R(36) * rho};
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                const R w = q == 0 ? wr[0] : (q < 5 ? wr[1] : wr[2]);
-                const R df = w * (R(3) * eD[q] + R(4.5) * eD[q] * eS[q] - DS);
-                fs[q] = fin9[q] + c.omega * (fe[q] - fin9[q]) + df;
+                const R shape = R(3) * eD[q] + R(4.5) * eD[q] * eS[q] - DS;
+                upd[q] = c.omega * neq[q] + wgt<D>(q) * rho_d * (D)shape;
             }
         } else {
             // Eq. 23 (Guo) or Eq. 31 (Li): equilibrium at v, bracket at v or v'.
-            equilibrium<R>(rho, vx, vy, fe);
+            eq_minus_f<R, D>(rho_d, vx, vy, f, neq);
             R bx = vx, by = vy;
             if constexpr (SCHEME == GUO_LI) {
                 const R cl = c.li / (pc * pc);
@@ -222,27 +206,25 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
             R B[9];
             guo_bracket<R>(Fx, Fy, bx, by, B);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) fs[q] = fin9[q] + c.omega * (fe[q] - fin9[q]) + c.kguo * B[q];
+            for (int q = 0; q < 9; ++q) upd[q] = c.omega * neq[q] + c.kguo * (D)B[q];
         }
     } else {
         // MRT, Eq. 34: m* = m - Lambda (m - m_eq) + (I - Lambda/2) S with m_eq = M f^eq(rho, v).
-        // Evaluated as f* = f - M^-1 [Lambda M (f - f^eq) - (I - Lambda/2) S] so that only
-        // non-equilibrium quantities go through the transform (FP32 accuracy).
-        equilibrium<R>(rho, vx, vy, fe);
-        R d[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) d[q] = fin9[q] - fe[q];
-        const R ax = d[1] + d[2] + d[3] + d[4], dg = d[5] + d[6] + d[7] + d[8];
-        const R d13 = d[1] - d[3], d24 = d[2] - d[4], d57 = d[5] - d[7], d86 = d[8] - d[6],
+        // Evaluated as f* = f + M^-1 [Lambda M (f^eq - f) + (I - Lambda/2) S] so that only
+        // non-equilibrium quantities go through the transform.
+        D d[9];
+        eq_minus_f<R, D>(rho_d, vx, vy, f, d);  // d = f^eq - f
+        const D ax = d[1] + d[2] + d[3] + d[4], dg = d[5] + d[6] + d[7] + d[8];
+        const D d13 = d[1] - d[3], d24 = d[2] - d[4], d57 = d[5] - d[7], d86 = d[8] - d[6],
                 d68 = d[6] - d[8];
-        R n[9];
+        D n[9];  // M (f^eq - f)
         n[0] = (d[0] + ax) + dg;
-        n[1] = -R(4) * d[0] - ax + R(2) * dg;
-        n[2] = R(4) * d[0] - R(2) * ax + dg;
+        n[1] = -D(4) * d[0] - ax + D(2) * dg;
+        n[2] = D(4) * d[0] - D(2) * ax + dg;
         n[3] = d13 + d57 + d86;
-        n[4] = -R(2) * d13 + d57 + d86;
+        n[4] = -D(2) * d13 + d57 + d86;
         n[5] = d24 + d57 + d68;
-        n[6] = -R(2) * d24 + d57 + d68;
+        n[6] = -D(2) * d24 + d57 + d68;
         n[7] = (d[1] + d[3]) - (d[2] + d[4]);
         n[8] = (d[5] + d[7]) - (d[6] + d[8]);
         // Guo's source in moment space, S = M B(v).
@@ -258,63 +240,269 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
             S[7] += (Xxx - Xyy) * c.lim[7];
             S[8] += Xxy * c.lim[8];
         }
-        R a[9];
-        const R Dinv[9] = {R(1) / R(9), R(1) / R(36), R(1) / R(36), R(1) / R(6), R(1) / R(12),
-                           R(1) / R(6), R(1) / R(12), R(1) / R(4), R(1) / R(4)};
+        D a[9];  // D^-1 [Lambda M (f^eq - f) + (I - Lambda/2) S]
+        const D Dinv[9] = {D(1) / D(9), D(1) / D(36), D(1) / D(36), D(1) / D(6), D(1) / D(12),
+                           D(1) / D(6), D(1) / D(12), D(1) / D(4), D(1) / D(4)};
 #pragma unroll
-        for (int k = 0; k < 9; ++k) a[k] = (c.s[k] * n[k] - c.hs[k] * S[k]) * Dinv[k];
+        for (int k = 0; k < 9; ++k) a[k] = (c.s[k] * n[k] + c.hs[k] * (D)S[k]) * Dinv[k];
         // M^-1 = M^T D^-1
-        const R c0 = a[0] - a[1] - R(2) * a[2];
-        const R c5 = a[0] + R(2) * a[1] + a[2];
-        const R gx = a[3] - R(2) * a[4], gy = a[5] - R(2) * a[6];
-        const R hx = a[3] + a[4], hy = a[5] + a[6];
-        fs[0] = fin9[0] - (a[0] - R(4) * a[1] + R(4) * a[2]);
-        fs[1] = fin9[1] - (c0 + gx + a[7]);
-        fs[2] = fin9[2] - (c0 + gy - a[7]);
-        fs[3] = fin9[3] - (c0 - gx + a[7]);
-        fs[4] = fin9[4] - (c0 - gy - a[7]);
-        fs[5] = fin9[5] - (c5 + hx + hy + a[8]);
-        fs[6] = fin9[6] - (c5 - hx + hy - a[8]);
-        fs[7] = fin9[7] - (c5 - hx - hy + a[8]);
-        fs[8] = fin9[8] - (c5 + hx - hy - a[8]);
+        const D c0 = a[0] - a[1] - D(2) * a[2];
+        const D c5 = a[0] + D(2) * a[1] + a[2];
+        const D gx = a[3] - D(2) * a[4], gy = a[5] - D(2) * a[6];
+        const D hx = a[3] + a[4], hy = a[5] + a[6];
+        upd[1] = c0 + gx + a[7];
+        upd[2] = c0 + gy - a[7];
+        upd[3] = c0 - gx + a[7];
+        upd[4] = c0 - gy - a[7];
+        upd[5] = c5 + hx + hy + a[8];
+        upd[6] = c5 - hx + hy - a[8];
+        upd[7] = c5 - hx - hy + a[8];
+        upd[8] = c5 + hx - hy - a[8];
     }
-
+#pragma unroll
+    for (int q = 1; q < 9; ++q) fs[q] = (float)((D)f[q] + upd[q]);
     // Every scheme conserves mass exactly (sum_q f*_q = rho); closing the rest population on
     // it keeps the binary rounding of the weights 4/9, 1/9, 1/36 from drifting the mass.
-    fs[0] = rho - (((fs[1] + fs[3]) + (fs[2] + fs[4])) + ((fs[5] + fs[7]) + (fs[6] + fs[8])));
+    fs[0] = (float)(rho_d - density<D>(D(0), (D)fs[1], (D)fs[2], (D)fs[3], (D)fs[4], (D)fs[5],
+                                       (D)fs[6], (D)fs[7], (D)fs[8]));
+}
 
-    // Push streaming, Eq. 36: f_q(x + e_q, t + 1) = f*_q(x, t), periodic.
-    const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-    const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
-    const size_t rc = (size_t)y * c.pitch, rn = (size_t)yn * c.pitch, rs = (size_t)ys * c.pitch;
-    fout[rc + x] = (float)fs[0];
-    fout[pl + rc + xe] = (float)fs[1];
-    fout[2 * pl + rn + x] = (float)fs[2];
-    fout[3 * pl + rc + xw] = (float)fs[3];
-    fout[4 * pl + rs + x] = (float)fs[4];
-    fout[5 * pl + rn + xe] = (float)fs[5];
-    fout[6 * pl + rn + xw] = (float)fs[6];
-    fout[7 * pl + rs + xw] = (float)fs[7];
-    fout[8 * pl + rs + xe] = (float)fs[8];
+__device__ __forceinline__ void put(float *p, float v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Push streaming, Eq. 36: f_q(x + e_q, t + 1) = f*_q(x, t), periodic.
+template <typename R, typename D>
+__device__ __forceinline__ void stream_out(float *__restrict__ fout, const StepConst<R, D> &c,
+                                           int x, int y, const float fs[9], bool nt) {
+    const int xe = x + 1 == c.nx ? 0 : x + 1, xw = x == 0 ? c.nx - 1 : x - 1;
+    const int yn = y + 1 == c.ny ? 0 : y + 1, ys = y == 0 ? c.ny - 1 : y - 1;
+    const size_t q = c.fq;
+    const size_t rc = (size_t)y * c.frow, rn = (size_t)yn * c.frow, rs = (size_t)ys * c.frow;
+    put(fout + rc + x, fs[0], nt);
+    put(fout + q + rc + xe, fs[1], nt);
+    put(fout + 2 * q + rn + x, fs[2], nt);
+    put(fout + 3 * q + rc + xw, fs[3], nt);
+    put(fout + 4 * q + rs + x, fs[4], nt);
+    put(fout + 5 * q + rn + xe, fs[5], nt);
+    put(fout + 6 * q + rn + xw, fs[6], nt);
+    put(fout + 7 * q + rs + xw, fs[7], nt);
+    put(fout + 8 * q + rs + xe, fs[8], nt);
+}
+
+__device__ __forceinline__ void load9(const float *__restrict__ f, size_t i, size_t fq, float v[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[q] = f[i + q * fq];
+}
+
+// Block index remapped so that consecutive tiles land on the same XCD (workgroups are dealt
+// round-robin to the eight XCDs, each with its own L2): neighbouring tiles then share the
+// psi halo rows and the partially written cache lines of the shifted planes in one L2.
+__device__ __forceinline__ int tile_id(int b, int nb, bool xcd) {
+    if (!xcd) return b;
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    const int per = full >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------------------
+// Two-pass step, pass 1: density and psi (Eq. 3, Eq. 29-30, Eq. 7), four nodes per thread
+// with 16-byte loads along x (rows are padded to 64 floats).
+// ---------------------------------------------------------------------------------------
+template <typename R, typename D>
+__global__ void __launch_bounds__(256) psi_kernel(const float *__restrict__ f,
+                                                  float *__restrict__ psi, StepConst<R, D> c) {
+    const int x4 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (x4 >= c.nx) return;
+    for (int y = blockIdx.y; y < c.ny; y += gridDim.y) {
+        const size_t i = (size_t)y * c.frow + x4;
+        float4 v[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] = *reinterpret_cast<const float4 *>(f + i + q * c.fq);
+        float4 out;
+        {
+            const float a[9] = {v[0].x, v[1].x, v[2].x, v[3].x, v[4].x, v[5].x, v[6].x, v[7].x, v[8].x};
+            out.x = c.psi_of(a);
+        }
+        {
+            const float a[9] = {v[0].y, v[1].y, v[2].y, v[3].y, v[4].y, v[5].y, v[6].y, v[7].y, v[8].y};
+            out.y = c.psi_of(a);
+        }
+        {
+            const float a[9] = {v[0].z, v[1].z, v[2].z, v[3].z, v[4].z, v[5].z, v[6].z, v[7].z, v[8].z};
+            out.z = c.psi_of(a);
+        }
+        {
+            const float a[9] = {v[0].w, v[1].w, v[2].w, v[3].w, v[4].w, v[5].w, v[6].w, v[7].w, v[8].w};
+            out.w = c.psi_of(a);
+        }
+        *reinterpret_cast<float4 *>(psi + (size_t)y * c.pitch + x4) = out;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Two-pass step, pass 2: fused force + collision + streaming on a TX x TY tile, psi of the
+// tile and a one-node halo staged in LDS.
+// ---------------------------------------------------------------------------------------
+template <typename R, typename D, int SCHEME, int COLL>
+__global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ fin,
+                                                     const float *__restrict__ psi,
+                                                     float *__restrict__ fout,
+                                                     StepConst<R, D> c) {
+    extern __shared__ float tile[];
+    const int TX = blockDim.x, TY = blockDim.y;
+    const int W = TX + 2;
+    const int nx = c.nx, ny = c.ny;
+    const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
+                          c.flags & kFlagXCD);
+    const int x0 = (b % gridDim.x) * TX, y0 = (b / gridDim.x) * TY;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < nx && y < ny;
+
+    // Populations first, so their latency overlaps the psi staging below.
+    float f[9];
+    if (active) load9(fin, (size_t)y * c.frow + x, c.fq, f);
+
+    // Stage psi of the tile and its one-node halo (periodic) in LDS.
+    const bool inner = x0 >= 1 && x0 + TX < nx && y0 >= 1 && y0 + TY < ny;
+    for (int ly = ty; ly < TY + 2; ly += TY) {
+        int gy = y0 + ly - 1;
+        if (!inner) gy = wrap_any(gy, ny);
+        const float *row = psi + (size_t)gy * c.pitch;
+        for (int lx = tx; lx < W; lx += TX) {
+            int gx = x0 + lx - 1;
+            if (!inner) gx = wrap_any(gx, nx);
+            tile[ly * W + lx] = row[gx];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const int lc = (ty + 1) * W + tx + 1;
+    const Nb<float> nb = {tile[lc],         tile[lc + 1],     tile[lc - 1],
+                      tile[lc + W],     tile[lc - W],     tile[lc + W + 1],
+                      tile[lc + W - 1], tile[lc - W - 1], tile[lc - W + 1]};
+    float fs[9];
+    collide<R, D, SCHEME, COLL>(f, nb, c, fs);
+    stream_out<R, D>(fout, c, x, y, fs, c.flags & kFlagNT);
+}
+
+// ---------------------------------------------------------------------------------------
+// One-pass step: a workgroup of TX threads owns a strip of TX columns and sweeps a segment of
+// H rows upwards.  psi is computed from the populations as each row is loaded and kept in a
+// four-row LDS ring (plus the two halo columns, computed by lanes 0 and 1), so every
+// population is read from memory once per step; only the halo columns and the row below and
+// above the segment are read twice.  Rows are software-pipelined two deep: while row y is
+// collided, row y+1 (loaded one iteration earlier) becomes psi and the loads of row y+2 are
+// in flight.  Same per-node arithmetic as the two-pass step, bit for bit.
+// ---------------------------------------------------------------------------------------
+template <typename R, typename D, int SCHEME, int COLL, int PF>
+__global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
+                                                    float *__restrict__ fout,
+                                                    StepConst<R, D> c, int H) {
+    extern __shared__ float ring[];  // 4 rows x (TX + 2)
+    const int TX = blockDim.x, W = TX + 2;
+    const int nx = c.nx, ny = c.ny;
+    const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
+                          c.flags & kFlagXCD);
+    const int x0 = (b % gridDim.x) * TX, y0 = (b / gridDim.x) * H;
+    const int tx = threadIdx.x;
+    const int na = nx - x0 < TX ? nx - x0 : TX;  // active columns of this strip
+    const bool active = tx < na;
+    const bool halo = tx < 2;                    // lanes 0 and 1 also own the halo columns
+    const int x = x0 + tx;
+    const int y1 = y0 + H < ny ? y0 + H : ny;
+    const size_t fq = c.fq, frow = c.frow;
+    const int hcol = tx == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + na == nx ? 0 : x0 + na);
+    const int hslot = tx == 0 ? 0 : na + 1;
+    const bool nt = c.flags & kFlagNT;
+    auto wrapy = [&](int yy) { return yy >= ny ? yy - ny : (yy < 0 ? yy + ny : yy); };
+    auto slot = [&](int yy_rel) { return ring + ((yy_rel + 1) & 3) * W; };
+
+    // PF = 2: rows y (fa), y+1 (fb) and y+2 (fc, loads in flight) in registers; halo lanes
+    // issue the loads of halo row y+2 at the top of iteration y and turn them into psi at its
+    // bottom, straight into the ring slot of row y+2 (that slot held row y-2, which no thread
+    // reads in iteration y; iteration y+1 reads it after its barrier).
+    // PF = 1: row y+1 is loaded and turned into psi at the top of iteration y.
+    float fa[9], fb[9], fc[9], hc[9];
+    {
+        const int ym = wrapy(y0 - 1), yp = wrapy(y0 + 1);
+        if (active) load9(fin, (size_t)ym * frow + x, fq, fc);
+        if (active) load9(fin, (size_t)y0 * frow + x, fq, fa);
+        if (active) slot(-1)[tx + 1] = c.psi_of(fc);
+        if (active) slot(0)[tx + 1] = c.psi_of(fa);
+        if (PF == 2 && active) load9(fin, (size_t)yp * frow + x, fq, fb);
+        if (halo) {
+            load9(fin, (size_t)ym * frow + hcol, fq, hc);
+            slot(-1)[hslot] = c.psi_of(hc);
+            load9(fin, (size_t)y0 * frow + hcol, fq, hc);
+            slot(0)[hslot] = c.psi_of(hc);
+            if (PF == 2) {
+                load9(fin, (size_t)yp * frow + hcol, fq, hc);
+                slot(1)[hslot] = c.psi_of(hc);
+            }
+        }
+    }
+    for (int y = y0; y < y1; ++y) {
+        float *rn = slot(y - y0 + 1);
+        bool more = false;
+        if constexpr (PF == 2) {
+            // Row y+2 is needed only while row y+1 is still inside the segment.
+            more = y + 2 <= y1;
+            if (more) {
+                const size_t r2 = (size_t)wrapy(y + 2) * frow;
+                if (active) load9(fin, r2 + x, fq, fc);
+                if (halo) load9(fin, r2 + hcol, fq, hc);
+            }
+        } else {
+            const size_t r1 = (size_t)wrapy(y + 1) * frow;
+            if (active) load9(fin, r1 + x, fq, fb);
+            if (halo) {
+                load9(fin, r1 + hcol, fq, hc);
+                rn[hslot] = c.psi_of(hc);
+            }
+        }
+        if (active) rn[tx + 1] = c.psi_of(fb);
+        __syncthreads();
+        if (active) {
+            const float *rs = slot(y - y0 - 1), *rc = slot(y - y0);
+            const int l = tx + 1;
+            const Nb<float> nb = {rc[l], rc[l + 1], rc[l - 1], rn[l], rs[l],
+                                  rn[l + 1], rn[l - 1], rs[l - 1], rs[l + 1]};
+            float fs[9];
+            collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
+            stream_out<R, D>(fout, c, x, y, fs, nt);
+        }
+        if (PF == 2 && halo && more) slot(y - y0 + 2)[hslot] = c.psi_of(hc);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            fa[q] = fb[q];
+            if (PF == 2) fb[q] = fc[q];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
 // Initial state, read-out and observables (FP64 arithmetic on the FP32 state).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) init_kernel(const double *__restrict__ rho0,
+__global__ void __launch_bounds__(256) init_kernel(Physics p, const double *__restrict__ rho0,
                                                    const double *__restrict__ u0,
-                                                   float *__restrict__ f, int nx, int ny,
-                                                   size_t pitch, size_t plane) {
+                                                   float *__restrict__ f) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    for (int y = blockIdx.y; y < ny; y += gridDim.y) {
-        const size_t k = (size_t)y * nx + x;
+    if (x >= p.nx) return;
+    for (int y = blockIdx.y; y < p.ny; y += gridDim.y) {
+        const size_t k = (size_t)y * p.nx + x;
         const double ux = u0 ? u0[2 * k] : 0.0, uy = u0 ? u0[2 * k + 1] : 0.0;
-        double fe[9];
-        equilibrium<double>(rho0[k], ux, uy, fe);
-        const size_t i = (size_t)y * pitch + x;
+        double s[9];
+        eq_shape<double>(ux, uy, s);
+        const size_t i = (size_t)y * p.frow + x;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[i + q * plane] = (float)fe[q];
+        for (int q = 0; q < 9; ++q) f[i + q * p.fq] = (float)(wgt<double>(q) * rho0[k] * (1.0 + s[q]));
     }
 }
 
@@ -326,14 +514,11 @@ struct NodeMacro {
 // rho and v = u + F/(2 rho) of node (x, y) from the populations and the psi plane, FP64.
 __device__ __forceinline__ NodeMacro node_macro(const Physics &p, const float *__restrict__ f,
                                                 const float *__restrict__ psi, int x, int y) {
-    const size_t pl = p.plane;
-    const size_t i = (size_t)y * p.pitch + x;
-    const double f0 = f[i], f1 = f[i + pl], f2 = f[i + 2 * pl], f3 = f[i + 3 * pl],
-                 f4 = f[i + 4 * pl], f5 = f[i + 5 * pl], f6 = f[i + 6 * pl], f7 = f[i + 7 * pl],
-                 f8 = f[i + 8 * pl];
-    const double rho = density<double>(f0, f1, f2, f3, f4, f5, f6, f7, f8);
-    const double jx = ((f1 - f3) + (f5 - f7)) + (f8 - f6);
-    const double jy = ((f2 - f4) + (f5 - f7)) + (f6 - f8);
+    float v[9];
+    load9(f, (size_t)y * p.frow + x, p.fq, v);
+    const double rho = density9<double>(v);
+    const double jx = (((double)v[1] - v[3]) + ((double)v[5] - v[7])) + ((double)v[8] - v[6]);
+    const double jy = (((double)v[2] - v[4]) + ((double)v[5] - v[7])) + ((double)v[6] - v[8]);
     const int xe = x + 1 == p.nx ? 0 : x + 1, xw = x == 0 ? p.nx - 1 : x - 1;
     const int yn = y + 1 == p.ny ? 0 : y + 1, ys = y == 0 ? p.ny - 1 : y - 1;
     auto P = [&](int xx, int yy) { return (double)psi[(size_t)yy * p.pitch + xx]; };
@@ -444,10 +629,9 @@ __global__ void __launch_bounds__(kStatsBlock) stats_final_kernel(Physics p, con
     if (threadIdx.x < kStatsFields) out[threadIdx.x] = sh[threadIdx.x][0];
     if (threadIdx.x == 0 || threadIdx.x == 1) {
         const int x = threadIdx.x == 0 ? xa : xb, y = threadIdx.x == 0 ? ya : yb;
-        const size_t i = (size_t)y * p.pitch + x, pl = p.plane;
-        out[kStatsFields + threadIdx.x] =
-            density<double>(f[i], f[i + pl], f[i + 2 * pl], f[i + 3 * pl], f[i + 4 * pl],
-                            f[i + 5 * pl], f[i + 6 * pl], f[i + 7 * pl], f[i + 8 * pl]);
+        float v[9];
+        load9(f, (size_t)y * p.frow + x, p.fq, v);
+        out[kStatsFields + threadIdx.x] = density9<double>(v);
     }
 }
 
@@ -464,22 +648,32 @@ __global__ void copy_tail_kernel(float *__restrict__ dst, const float *__restric
     if (i < n) dst[i] = src[i];
 }
 
-template <typename R>
-StepConst<R> make_const(const Physics &p) {
-    StepConst<R> c{};
+// ---------------------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------------------
+template <typename R, typename D>
+StepConst<R, D> make_const(const Physics &p, int flags) {
+    StepConst<R, D> c{};
     c.nx = p.nx;
     c.ny = p.ny;
     c.pitch = p.pitch;
-    c.plane = p.plane;
-    c.gA = (R)(-p.G * p.A / 2.0);
-    c.gB = (R)(-p.G * (1.0 - p.A));
-    c.omega = (R)(1.0 / p.tau);
-    c.kguo = (R)(1.0 - 1.0 / (2.0 * p.tau));
+    c.frow = p.frow;
+    c.fq = p.fq;
+    c.flags = flags;
+    c.bq = (D)p.b_quarter;
+    c.RT = (D)p.RT;
+    c.a = (D)p.a;
+    c.K = (D)p.K;
+    c.two_over_G = (D)(2.0 / p.G);
+    c.gA = (D)(-p.G * p.A / 2.0);
+    c.gB = (D)(-p.G * (1.0 - p.A));
+    c.omega = (D)(1.0 / p.tau);
+    c.kguo = (D)(1.0 - 1.0 / (2.0 * p.tau));
     c.li = (R)(p.sigma / (p.tau - 0.5));
     c.li2 = (R)(2.0 * p.sigma);
     for (int k = 0; k < 9; ++k) {
-        c.s[k] = (R)p.s[k];
-        c.hs[k] = (R)(1.0 - p.s[k] / 2.0);
+        c.s[k] = (D)p.s[k];
+        c.hs[k] = (D)(1.0 - p.s[k] / 2.0);
         c.lim[k] = (R)(1.0 / (1.0 / p.s[k] - 0.5));
     }
     return c;
@@ -489,54 +683,94 @@ dim3 row_grid(int nx, int ny, int block) {
     return dim3((unsigned)((nx + block - 1) / block), (unsigned)(ny < 65535 ? ny : 65535));
 }
 
-template <typename R>
-hipError_t fused_dispatch(const Physics &p, int tx, int ty, const float *fin, const float *psi,
+// Instantiates KERNEL<R, D, scheme, collision EXTRA> for the run-time scheme and collision;
+// EXTRA is empty or a further template argument list starting with a comma.
+#define PPLBM_DISPATCH_X(KERNEL, R, D, EXTRA, p, grid, block, lds, s, ...)                        \
+    do {                                                                                        \
+        if ((p).coll == BGK) {                                                                  \
+            if ((p).scheme == EDM)                                                              \
+                hipLaunchKernelGGL((KERNEL<R, D, EDM, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
+            else if ((p).scheme == GUO)                                                         \
+                hipLaunchKernelGGL((KERNEL<R, D, GUO, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
+            else                                                                                \
+                hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__); \
+        } else {                                                                                \
+            if ((p).scheme == GUO)                                                              \
+                hipLaunchKernelGGL((KERNEL<R, D, GUO, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
+            else                                                                                \
+                hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__); \
+        }                                                                                       \
+    } while (0)
+#define PPLBM_NOEXTRA
+#define PPLBM_PF1 , 1
+#define PPLBM_PF2 , 2
+#define PPLBM_DISPATCH(KERNEL, R, D, p, grid, block, lds, s, ...) \
+    PPLBM_DISPATCH_X(KERNEL, R, D, PPLBM_NOEXTRA, p, grid, block, lds, s, __VA_ARGS__)
+
+template <typename R, typename D>
+hipError_t psi_dispatch(const Physics &p, int flags, const float *fin, float *psi, hipStream_t s) {
+    const StepConst<R, D> c = make_const<R, D>(p, flags);
+    const dim3 grid((unsigned)((p.nx + 4 * 256 - 1) / (4 * 256)),
+                    (unsigned)(p.ny < 65535 ? p.ny : 65535));
+    hipLaunchKernelGGL((psi_kernel<R, D>), grid, dim3(256), 0, s, fin, psi, c);
+    return hipGetLastError();
+}
+
+template <typename R, typename D>
+hipError_t fused_dispatch(const Physics &p, const Launch &L, const float *fin, const float *psi,
                           float *fout, hipStream_t s) {
-    const StepConst<R> c = make_const<R>(p);
-    const dim3 block(tx, ty);
-    const dim3 grid((unsigned)((p.nx + tx - 1) / tx), (unsigned)((p.ny + ty - 1) / ty));
-    const size_t lds = (size_t)(tx + 2) * (ty + 2) * sizeof(float);
-    if (p.coll == BGK) {
-        if (p.scheme == EDM)
-            hipLaunchKernelGGL((fused_kernel<R, EDM, BGK>), grid, block, lds, s, fin, psi, fout, c);
-        else if (p.scheme == GUO)
-            hipLaunchKernelGGL((fused_kernel<R, GUO, BGK>), grid, block, lds, s, fin, psi, fout, c);
-        else
-            hipLaunchKernelGGL((fused_kernel<R, GUO_LI, BGK>), grid, block, lds, s, fin, psi, fout, c);
-    } else {
-        if (p.scheme == GUO)
-            hipLaunchKernelGGL((fused_kernel<R, GUO, MRT>), grid, block, lds, s, fin, psi, fout, c);
-        else
-            hipLaunchKernelGGL((fused_kernel<R, GUO_LI, MRT>), grid, block, lds, s, fin, psi, fout, c);
-    }
+    const StepConst<R, D> c = make_const<R, D>(p, L.flags);
+    const dim3 grid((unsigned)((p.nx + L.tx - 1) / L.tx), (unsigned)((p.ny + L.ty - 1) / L.ty));
+    const size_t lds = (size_t)(L.tx + 2) * (L.ty + 2) * sizeof(float);
+    PPLBM_DISPATCH(fused_kernel, R, D, p, grid, dim3(L.tx, L.ty), lds, s, fin, psi, fout, c);
+    return hipGetLastError();
+}
+
+template <typename R, typename D>
+hipError_t sweep_dispatch(const Physics &p, const Launch &L, const float *fin, float *fout,
+                          hipStream_t s) {
+    const StepConst<R, D> c = make_const<R, D>(p, L.flags);
+    const dim3 grid((unsigned)((p.nx + L.tx - 1) / L.tx), (unsigned)((p.ny + L.ty - 1) / L.ty));
+    const size_t lds = 4 * (size_t)(L.tx + 2) * sizeof(float);
+    if (L.flags & kFlagShallow)
+        PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF1, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+    else
+        PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF2, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_psi(const Physics &p, bool fp64, const float *f, float *psi, hipStream_t s) {
-    const dim3 grid = row_grid(p.nx, p.ny, 256);
-    const double two_over_G = 2.0 / p.G;
-    if (fp64)
-        hipLaunchKernelGGL(psi_kernel<double>, grid, dim3(256), 0, s, f, psi, p.nx, p.ny, p.pitch,
-                           p.plane, p.b_quarter, p.RT, p.a, p.K, two_over_G);
-    else
-        hipLaunchKernelGGL(psi_kernel<float>, grid, dim3(256), 0, s, f, psi, p.nx, p.ny, p.pitch,
-                           p.plane, (float)p.b_quarter, (float)p.RT, (float)p.a, (float)p.K,
-                           (float)two_over_G);
-    return hipGetLastError();
+hipError_t launch_psi(const Physics &p, int prec, int flags, const float *f, float *psi,
+                      hipStream_t s) {
+    switch (prec) {
+    case kPrecF32: return psi_dispatch<float, float>(p, flags, f, psi, s);
+    case kPrecF64: return psi_dispatch<double, double>(p, flags, f, psi, s);
+    default: return psi_dispatch<float, double>(p, flags, f, psi, s);
+    }
 }
 
-hipError_t launch_fused(const Physics &p, bool fp64, int tx, int ty, const float *fin,
+hipError_t launch_fused(const Physics &p, int prec, const Launch &L, const float *fin,
                         const float *psi, float *fout, hipStream_t s) {
-    return fp64 ? fused_dispatch<double>(p, tx, ty, fin, psi, fout, s)
-                : fused_dispatch<float>(p, tx, ty, fin, psi, fout, s);
+    switch (prec) {
+    case kPrecF32: return fused_dispatch<float, float>(p, L, fin, psi, fout, s);
+    case kPrecF64: return fused_dispatch<double, double>(p, L, fin, psi, fout, s);
+    default: return fused_dispatch<float, double>(p, L, fin, psi, fout, s);
+    }
+}
+
+hipError_t launch_sweep(const Physics &p, int prec, const Launch &L, const float *fin,
+                        float *fout, hipStream_t s) {
+    switch (prec) {
+    case kPrecF32: return sweep_dispatch<float, float>(p, L, fin, fout, s);
+    case kPrecF64: return sweep_dispatch<double, double>(p, L, fin, fout, s);
+    default: return sweep_dispatch<float, double>(p, L, fin, fout, s);
+    }
 }
 
 hipError_t launch_init(const Physics &p, const double *rho0, const double *u0, float *f,
                        hipStream_t s) {
-    hipLaunchKernelGGL(init_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, rho0, u0, f,
-                       p.nx, p.ny, p.pitch, p.plane);
+    hipLaunchKernelGGL(init_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, p, rho0, u0, f);
     return hipGetLastError();
 }
 

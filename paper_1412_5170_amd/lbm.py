@@ -19,7 +19,10 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ENOTCONVERGED, LBM_
 LBM_EOS_CARNAHAN_STARLING = 0
 LBM_FORCE_EDM, LBM_FORCE_GUO, LBM_FORCE_GUO_LI = 0, 1, 2
 LBM_COLL_BGK, LBM_COLL_MRT = 0, 1
-LBM_PREC_F32, LBM_PREC_F64 = 0, 1
+LBM_PREC_F32, LBM_PREC_F64, LBM_PREC_MIXED = 0, 1, 2
+LBM_LAYOUT_PLANES, LBM_LAYOUT_ROWS = 0, 1
+LBM_KERNEL_TWO_PASS, LBM_KERNEL_SWEEP = 0, 1
+LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_XCD_ORDER, LBM_LAUNCH_SHALLOW = 1, 2, 4
 
 SCHEMES = {"EDM": LBM_FORCE_EDM, "GUO": LBM_FORCE_GUO, "GUO_LI": LBM_FORCE_GUO_LI}
 COLLISIONS = {"BGK": LBM_COLL_BGK, "MRT": LBM_COLL_MRT}
@@ -67,7 +70,11 @@ _SIG = {
     "lbm_attach": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lbm_set_stream": (ctypes.c_int, [_P, _P]),
     "lbm_set_precision": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_set_layout": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_strides": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_size_t)] * 2),
     "lbm_set_tile": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "lbm_set_launch": (ctypes.c_int, [_P] + [ctypes.c_int] * 4),
+    "lbm_get_launch": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_int)] * 4),
     "lbm_set_probes": (ctypes.c_int, [_P] + [ctypes.c_int] * 4),
     "lbm_init": (ctypes.c_int, [_P, _D, _D]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -138,8 +145,8 @@ def eos_maxwell(eos: lbm_eos):
 class Lattice:
     """One periodic lattice whose buffers and stream come from torch (device memory only)."""
 
-    def __init__(self, nx, ny, eos, force, collision, tau, precision=LBM_PREC_F64,
-                 tile=None, device="cuda:0", stream=None):
+    def __init__(self, nx, ny, eos, force, collision, tau, precision=LBM_PREC_MIXED,
+                 tile=None, device="cuda:0", stream=None, layout=LBM_LAYOUT_ROWS):
         import torch  # torch supplies device memory and the stream
         self.nx, self.ny = nx, ny
         h = _P()
@@ -158,6 +165,7 @@ class Lattice:
         check(lbm_attach(h, self.f_a.data_ptr(), self.f_b.data_ptr(), self.psi.data_ptr(),
                          self.stream.cuda_stream), h)
         check(lbm_set_precision(h, precision), h)
+        check(lbm_set_layout(h, layout), h)
         if tile is not None:
             check(lbm_set_tile(h, *tile), h)
 
@@ -204,6 +212,14 @@ class Lattice:
 
     def set_tile(self, tx, ty):
         check(lbm_set_tile(self.h, tx, ty), self.h)
+
+    def set_launch(self, kernel, tx, ty, flags=0):
+        check(lbm_set_launch(self.h, kernel, tx, ty, flags), self.h)
+
+    def get_launch(self):
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lbm_get_launch(self.h, *(ctypes.byref(x) for x in v)), self.h)
+        return tuple(x.value for x in v)
 
     def set_precision(self, precision):
         check(lbm_set_precision(self.h, precision), self.h)

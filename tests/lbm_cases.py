@@ -33,12 +33,12 @@ def oracle_params(wl):
                     K=wl["K"], A=wl["A"], sigma=wl["sigma"], s=s)
 
 
-def gpu_lattice(L, wl, precision, tile=None):
+def gpu_lattice(L, wl, precision, tile=None, layout=1):
     eos = L.make_eos(wl["T_over_Tc"], K=wl["K"])
     force = L.make_force(wl["scheme"], A=wl["A"], sigma=wl["sigma"])
     coll = L.make_collision(wl["collision"], s=wl.get("s5", MRT_RATES))
     return L.Lattice(wl["nx"], wl["ny"], eos, force, coll, wl["tau"], precision=precision,
-                     tile=tile)
+                     tile=tile, layout=layout)
 
 
 def initial_density(wl):
