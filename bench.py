@@ -4,12 +4,18 @@ Workload (default): the 4096 x 4096 periodic static droplet, radius 600, tanh in
 width 5 from the Maxwell coexistence densities at T/Tc = 0.5 (ratio ~725), MRT collision
 (s_rho = s_j = 1, s_e = s_eps = s_q = 1.1, s_nu = 1/tau, tau = 1), Guo forcing with Li's
 modified force term (sigma = 0.125), Carnahan-Starling EOS rescaled by K = 1/49.
-A step is one full time step (density/psi pass + fused force/collide/stream pass); the FP64
-observables reduction runs every --stats-every steps inside the timed region, as a production
-run would.  Inputs are resident in HBM before timing starts.
+A step is one full time step -- by default the one-pass sweep kernel (psi recomputed from the
+populations, force, forcing, collision and streaming in one launch); --kernel two_pass runs the
+density/psi pass and the fused pass instead -- and the FP64 observables reduction runs every
+--stats-every steps inside the timed region, as a production run would.  Inputs are resident in
+HBM before timing starts.
 
-Prints ONE JSON line: MLUPS, HBM roofline of the dominant (fused) kernel measured with HIP
-events on the lattice's stream, and the FP64 oracle's MLUPS on the host cores (cpu_baseline).
+Prints ONE JSON line: MLUPS, the HBM roofline of the dominant kernel measured with HIP events
+on the lattice's stream (algorithmic bytes per launch / average launch time), the same for the
+two-pass variant, and the FP64 oracle's MLUPS on the host cores (cpu_baseline).
+
+--copy-probe instead times the library's plain copy kernel on a buffer the size of one
+population buffer (the scale reference for the HBM counters).
 """
 from __future__ import annotations
 
@@ -24,8 +30,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public spec
-FUSED_BYTES_PER_NODE = 76      # 9 FP32 populations read + 9 written + psi read once
-PSI_BYTES_PER_NODE = 40        # 9 FP32 populations read + psi written
+SWEEP_BYTES_PER_NODE = 72      # one-pass step: 9 FP32 populations read + 9 written
+FUSED_BYTES_PER_NODE = 76      # two-pass, pass 2: 9 populations read + 9 written + psi read
+PSI_BYTES_PER_NODE = 40        # two-pass, pass 1: 9 populations read + psi written
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -35,8 +42,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="droplet_4096_mrt")
-    ap.add_argument("--precision", default="f64", choices=["f32", "f64"])
-    ap.add_argument("--tile", default=None, help="tx,ty of the fused pass")
+    ap.add_argument("--precision", default="mixed", choices=["f32", "f64", "mixed"])
+    ap.add_argument("--kernel", default="sweep", choices=["sweep", "two_pass"])
+    ap.add_argument("--launch", default=None,
+                    help="tx,ty[,flags] of the kernel (default: the library's choice)")
+    ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
+    ap.add_argument("--alt-steps", type=int, default=200,
+                    help="steps of the two-pass variant timed beside the main result (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-every", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle baseline sample")
@@ -46,6 +59,12 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1412_5170_amd", "csrc", "lbm_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on a bounded sample of the same physics: a 512 x 512 cut of the
     workload (droplet radius scaled with the side), as many steps as fit the budget."""
@@ -53,17 +72,15 @@ def cpu_baseline(wl, budget_s):
     from oracle import thermo as TH
     from paper_1412_5170_amd import inputs
 
-    n = 512
-    scale = n / wl["nx"]
-    sample = dict(wl, nx=n, ny=n, R=wl.get("R", 0) * scale if wl["init"] == "droplet" else 0)
-    if wl["init"] == "slab":
+    if wl["init"] == "droplet" and wl["nx"] > 512:
+        sample = dict(wl, nx=512, ny=512, R=wl["R"] * 512 / wl["nx"])
+    else:
         sample = dict(wl)
-        n = None
     g, l, _ = TH.maxwell(wl["T_over_Tc"])
     rho0 = inputs.initial_density(sample, l, g)
     tau = wl["tau"]
-    s = wl.get("s", (1.0,) * 9)
-    s = (s[0], s[1], s[2], s[3], s[4], s[5], s[6], 1 / tau, 1 / tau)
+    s = wl.get("s", (1.0, 1.1, 1.1, 1.0, 1.1))
+    s = (s[0], s[1], s[2], s[3], s[4], s[3], s[4], 1 / tau, 1 / tau)
     p = O.Params(nx=sample["nx"], ny=sample["ny"], T=TH.temperature(wl["T_over_Tc"]), tau=tau,
                  scheme=getattr(O, wl["scheme"]), collision=getattr(O, wl["collision"]),
                  K=wl["K"], A=wl["A"], sigma=wl["sigma"], s=s)
@@ -78,8 +95,79 @@ def cpu_baseline(wl, budget_s):
     nodes = sample["nx"] * sample["ny"]
     return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.threads(),
             "kind": "oracle",
-            "sample": f"{sample['nx']}x{sample['ny']} cut of the workload (same physics), "
-                      f"{steps} FP64 steps, {dt:.1f} s"}
+            "sample": f"{sample['nx']}x{sample['ny']} lattice of the workload's physics (droplet "
+                      f"radius scaled with the side), {steps} FP64 steps, {dt:.1f} s"}
+
+
+PRECISIONS = {"f32": 0, "f64": 1, "mixed": 2}
+DTYPE = {"f32": "f32", "f64": "f64 (f32 storage)", "mixed": "f32+f64 mixed (f32 storage)"}
+
+
+def make_lattice(lbm, wl, args, kernel):
+    eos = lbm.make_eos(wl["T_over_Tc"], K=wl["K"])
+    s = wl.get("s", (1.0, 1.1, 1.1, 1.0, 1.1))
+    lat = lbm.Lattice(wl["nx"], wl["ny"], eos,
+                      lbm.make_force(wl["scheme"], A=wl["A"], sigma=wl["sigma"]),
+                      lbm.make_collision(wl["collision"], s=s[:5]), wl["tau"],
+                      precision=PRECISIONS[args.precision],
+                      layout=lbm.LBM_LAYOUT_ROWS if args.layout == "rows" else lbm.LBM_LAYOUT_PLANES)
+    k, tx, ty, fl = lat.get_launch()
+    if kernel == "two_pass":
+        k, tx, ty, fl = lbm.LBM_KERNEL_TWO_PASS, 128, 8, lbm.LBM_LAUNCH_XCD_ORDER
+    if args.launch and kernel == args.kernel:
+        v = [int(t) for t in args.launch.split(",")]
+        tx, ty = v[0], v[1]
+        fl = v[2] if len(v) > 2 else fl
+    lat.set_launch(lbm.LBM_KERNEL_SWEEP if kernel == "sweep" else lbm.LBM_KERNEL_TWO_PASS,
+                   tx, ty, fl)
+    return lat
+
+
+def timed(lat, steps, stats_every, torch, timing=True):
+    """Run `steps` steps (the observables reduction every `stats_every`); returns wall seconds
+    and the library's per-kernel event totals."""
+    if timing:
+        lat.timing_enable(True)
+        lat.timing()                                  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(stats_every or steps, steps - done)
+        lat.step(k)
+        done += k
+        if stats_every and done % stats_every == 0:
+            lat.stats()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ev = None
+    if timing:
+        ev = lat.timing()
+        lat.timing_enable(False)
+    return elapsed, ev
+
+
+def copy_probe(args):
+    import torch
+
+    from paper_1412_5170_amd import inputs, lbm
+    wl = inputs.WORKLOADS[args.workload]
+    n = 9 * wl["nx"] * wl["ny"]
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        lbm.check(lbm.lbm_copy_f32(dst.data_ptr(), src.data_ptr(), n, stream))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps)
+    for _ in range(reps):
+        lbm.check(lbm.lbm_copy_f32(dst.data_ptr(), src.data_ptr(), n, stream))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe": {"bytes_read": 4 * n, "bytes_written": 4 * n,
+                                     "us": round(dt * 1e6, 2),
+                                     "GBps": round(8 * n / dt / 1e9, 1)}}), flush=True)
 
 
 def main():
@@ -88,85 +176,83 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design note, not code)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args)
+        return
 
     import torch
 
     from paper_1412_5170_amd import inputs, lbm
 
     wl = dict(inputs.WORKLOADS[args.workload])
-    eos = lbm.make_eos(wl["T_over_Tc"], K=wl["K"])
-    g, l = lbm.eos_maxwell(eos)
+    g, l = lbm.eos_maxwell(lbm.make_eos(wl["T_over_Tc"], K=wl["K"]))
     rho0 = inputs.initial_density(wl, l, g)
-    s = wl.get("s", (1.0, 1.1, 1.1, 1.0, 1.1))
-    lat = lbm.Lattice(wl["nx"], wl["ny"], eos, lbm.make_force(wl["scheme"], A=wl["A"],
-                                                            sigma=wl["sigma"]),
-                      lbm.make_collision(wl["collision"], s=s[:5]), wl["tau"],
-                      precision=lbm.LBM_PREC_F64 if args.precision == "f64" else lbm.LBM_PREC_F32,
-                      tile=tuple(int(v) for v in args.tile.split(",")) if args.tile else None)
-    lat.init(rho0)
-    del rho0
     nodes = wl["nx"] * wl["ny"]
-    print(f"bench: {args.workload} {wl['nx']}x{wl['ny']} {args.precision}, warmup {args.warmup}",
-          file=sys.stderr, flush=True)
+    timing = not args.no_timing
+
+    lat = make_lattice(lbm, wl, args, args.kernel)
+    launch = lat.get_launch()
+    lat.init(rho0)
+    print(f"bench: {args.workload} {wl['nx']}x{wl['ny']} {args.precision} {args.kernel} "
+          f"launch {launch}, warmup {args.warmup}", file=sys.stderr, flush=True)
     lat.step(args.warmup)
     st0 = lat.stats()
-    torch.cuda.synchronize()
-
-    if not args.no_timing:
-        lat.timing_enable(True)
-        lat.timing()                                  # reset
-    done = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    while done < args.steps:
-        k = min(args.stats_every, args.steps - done)
-        lat.step(k)
-        done += k
-        if args.stats_every and done % args.stats_every == 0:
-            st = lat.stats()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    psi_ms = fused_ms = None
-    if not args.no_timing:
-        psi_ms, fused_ms, nt = lat.timing()
-        lat.timing_enable(False)
+    elapsed, ev = timed(lat, args.steps, args.stats_every, torch, timing)
     st = lat.stats()
     print(f"bench: {args.steps} steps in {elapsed:.3f} s; mass drift "
           f"{(st['mass'] - st0['mass']) / st0['mass']:.2e}; us_max {st['us_max']:.3e}; "
           f"ratio {st['ratio']:.2f}", file=sys.stderr, flush=True)
+    del lat
 
-    mlups = nodes * args.steps / elapsed / 1e6
-    roof = None
-    if fused_ms is not None:
-        avg_fused_s = fused_ms / 1e3 / nt
-        avg_psi_s = psi_ms / 1e3 / nt
-        achieved = FUSED_BYTES_PER_NODE * nodes / avg_fused_s / 1e9
-        traffic = None
+    def roofline(kernel, ev):
+        psi_ms, main_ms, nt = ev
+        avg = main_ms / 1e3 / nt
+        per_node = SWEEP_BYTES_PER_NODE if kernel == "sweep" else FUSED_BYTES_PER_NODE
+        achieved = per_node * nodes / avg / 1e9
+        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+             "kernel": "sweep_kernel" if kernel == "sweep" else "fused_kernel",
+             "bytes_per_node": per_node, "avg_us": round(avg * 1e6, 2)}
+        if kernel == "two_pass":
+            pavg = psi_ms / 1e3 / nt
+            r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),
+                             "achieved": round(PSI_BYTES_PER_NODE * nodes / pavg / 1e9, 1)}
         if os.path.exists(PROFILE_TRAFFIC):
             t = json.load(open(PROFILE_TRAFFIC))
-            if t.get("workload") == args.workload and t.get("precision") == args.precision:
-                traffic = t.get("fused_bytes_per_launch")
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "fused_kernel", "avg_us": round(avg_fused_s * 1e6, 2),
-                "psi_pass": {"avg_us": round(avg_psi_s * 1e6, 2),
-                             "achieved": round(PSI_BYTES_PER_NODE * nodes / avg_psi_s / 1e9, 1)}}
+            key = f"{args.workload}/{kernel}/{args.precision}/{args.layout}"
+            # Counters are only valid for the kernel source they were taken on.
+            if key in t and t[key]["kernel_sha256_16"] == kernel_source_hash():
+                r["traffic"] = t[key]["bytes_per_launch"]
+                r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] /
+                                                      (per_node * nodes), 4)
+        return r
+
+    mlups = nodes * args.steps / elapsed / 1e6
     out = {
         "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "f32" else "f64 (f32 storage)",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "nx": wl["nx"], "ny": wl["ny"],
                    "collision": wl["collision"], "scheme": wl["scheme"],
                    "T_over_Tc": wl["T_over_Tc"], "K": wl["K"], "tau": wl["tau"],
+                   "kernel": args.kernel, "launch": list(launch), "layout": args.layout,
                    "stats_every": args.stats_every, "parallelism": "single GPU"},
-        "roofline": roof,
+        "roofline": roofline(args.kernel, ev) if ev else None,
     }
-    if not args.no_cpu_baseline:
+    alt = "two_pass" if args.kernel == "sweep" else "sweep"
+    if timing and args.alt_steps:
+        lat = make_lattice(lbm, wl, args, alt)
+        lat.init(rho0)
+        lat.step(args.warmup)
+        el2, ev2 = timed(lat, args.alt_steps, args.stats_every, torch, True)
         del lat
-        torch.cuda.empty_cache()
+        out["alternative"] = {"kernel": alt, "MLUPS": round(nodes * args.alt_steps / el2 / 1e6, 1),
+                              "roofline": roofline(alt, ev2)}
+    del rho0
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
