@@ -200,6 +200,60 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 int lbm_timing_enable(lbm_t *h, int enable);
 int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps);
 
+/* ---- batched sweep ---------------------------------------------------------------------------
+ * Many independent periodic lattices, each with its own size, EOS temperature and rescale,
+ * force, collision and relaxation time (the parameter sweeps of Sec. 4 as one job), advanced
+ * together: one persistent launch per time step walks a shared device list of tiles (strip of
+ * tx columns x segment of rows of one lattice); blocks of steps are captured once in a hipGraph
+ * and replayed; lattices that converge or go unstable are dropped from the tile list in device
+ * memory between replays.  Per-node arithmetic is the single-lattice sweep's (mixed precision,
+ * row-interleaved layout), so each lattice evolves bitwise as it would alone.  The batch owns
+ * its device memory and a HIP stream of its own (default priority). */
+typedef struct lbm_batch lbm_batch_t;
+
+/* count lattices; arrays of count entries.  Validation as lbm_create. */
+int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos,
+                     const lbm_force *force, const lbm_collision *collision, const double *tau,
+                     lbm_batch_t **out);
+void lbm_batch_destroy(lbm_batch_t *b);
+
+/* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups (0: one per
+ * tile up to 2048), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW (default SHALLOW). */
+int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
+
+/* Segment height (rows per tile) of lattice i (default 32); the autotuner sets it per size. */
+int lbm_batch_set_segment(lbm_batch_t *b, int i, int rows);
+
+/* f = f^eq(rho0, u0) for lattice i (host FP64 [ny][nx], u0 [ny][nx][2] or NULL); makes it
+ * active and resets its step count. */
+int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0);
+
+/* Include (1) or exclude (0) an initialised lattice from stepping. */
+int lbm_batch_set_active(lbm_batch_t *b, int i, int active);
+
+/* n (even) steps of every active lattice, asynchronously on the batch stream. */
+int lbm_batch_step(lbm_batch_t *b, int n);
+
+/* FP64 observables of every active lattice into out[i] (out has count entries); track_dv as in
+ * lbm_stats.  Synchronises.  LBM_EUNSTABLE if any lattice has non-finite nodes. */
+int lbm_batch_stats(lbm_batch_t *b, int track_dv, lbm_stats_t *out);
+
+/* Step every active lattice until max_x |v(t) - v(t - check_every)|_inf / check_every < tol
+ * (converged, status 0), a node goes non-finite (LBM_EUNSTABLE) or max_steps is reached
+ * (LBM_ENOTCONVERGED); check_every even.  steps_out / status_out: count entries (either may be
+ * NULL).  Lattices already inactive keep status LBM_ESTATE. */
+int lbm_batch_run(lbm_batch_t *b, double tol, int check_every, long long max_steps,
+                  long long *steps_out, int *status_out);
+
+/* rho and v of lattice i (as lbm_read); its populations as FP32 [9][ny][nx]. */
+int lbm_batch_read(lbm_batch_t *b, int i, double *rho, double *u);
+int lbm_batch_populations(lbm_batch_t *b, int i, float *f);
+
+/* Steps taken by lattice i (-1 for a bad index); wait for the batch stream; error text. */
+long long lbm_batch_steps(const lbm_batch_t *b, int i);
+int lbm_batch_sync(lbm_batch_t *b);
+const char *lbm_batch_last_error(const lbm_batch_t *b);
+
 /* ---- EOS helpers (host only) -------------------------------------------------------------- */
 
 /* Exact critical point of Eq. 29 (independent of K): dp/drho = d2p/drho2 = 0. */

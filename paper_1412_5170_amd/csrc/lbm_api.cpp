@@ -248,25 +248,17 @@ int ensure_stats(lbm *h) {
 
 }  // namespace
 
-extern "C" {
+namespace pplbm {
 
-int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
-               const lbm_collision *collision, double tau, lbm_t **out) {
-    if (!out) return LBM_EINVAL;
-    *out = nullptr;
-    std::string why;
-    int rc = validate(nx, ny, eos, force, collision, tau, &why);
+int make_physics(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+                 const lbm_collision *collision, double tau, Physics *out, double *T_out,
+                 std::string *why) {
+    int rc = validate(nx, ny, eos, force, collision, tau, why);
     if (rc) return rc;
-    lbm *h = new (std::nothrow) lbm();
-    if (!h) return LBM_ENOMEM;
-    h->eos = *eos;
-    h->force = *force;
-    h->coll = *collision;
-    h->tau = tau;
     double rc_, Tc, pc;
     critical(eos->a, eos->b, eos->R, &rc_, &Tc, &pc);
-    h->T = eos->T_over_Tc * Tc;
-    Physics &p = h->p;
+    const double T = eos->T_over_Tc * Tc;
+    Physics p{};
     p.nx = nx;
     p.ny = ny;
     p.pitch = ((size_t)nx + 63) / 64 * 64;
@@ -274,7 +266,7 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     p.frow = 9 * p.pitch;  // LBM_LAYOUT_ROWS
     p.fq = p.pitch;
     p.b_quarter = eos->b / 4.0;
-    p.RT = eos->R * h->T;
+    p.RT = eos->R * T;
     p.a = eos->a;
     p.K = eos->K;
     p.G = force->G;
@@ -291,6 +283,32 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     } else {
         for (double &s : p.s) s = snu;
     }
+    *out = p;
+    if (T_out) *T_out = T;
+    return LBM_OK;
+}
+
+}  // namespace pplbm
+
+extern "C" {
+
+int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+               const lbm_collision *collision, double tau, lbm_t **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    Physics p;
+    double T;
+    std::string why;
+    int rc = pplbm::make_physics(nx, ny, eos, force, collision, tau, &p, &T, &why);
+    if (rc) return rc;
+    lbm *h = new (std::nothrow) lbm();
+    if (!h) return LBM_ENOMEM;
+    h->eos = *eos;
+    h->force = *force;
+    h->coll = *collision;
+    h->tau = tau;
+    h->T = T;
+    h->p = p;
     h->xa = nx / 2;
     h->ya = ny / 2;
     h->launch = default_launch(nx, ny);

@@ -1,0 +1,456 @@
+// Batched sweep runtime (include/pplbm.h, lbm_batch_*): many independent periodic lattices --
+// each with its own size, EOS temperature and rescale, forcing, collision and relaxation time --
+// advanced together, one launch per time step over a shared device tile list; blocks of steps
+// are captured once in a hipGraph and replayed; FP64 observables per lattice at every check;
+// converged or unstable lattices are dropped from the tile list in device memory between
+// replays, so the captured graph stays valid.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pplbm.h"
+#include "lbm_internal.h"
+
+using pplbm::Physics;
+
+struct lbm_batch {
+    int count = 0;
+    std::vector<Physics> phys;
+    std::vector<float *> f0, f1, vprev;
+    std::vector<int> seg_rows;       // segment height of each lattice's tiles
+    std::vector<char> active;
+    std::vector<char> initialised;
+    std::vector<long long> steps;
+    std::vector<char> vprev_valid;
+    std::vector<int> xa, ya, xb, yb;
+    void *desc = nullptr;            // device BatchLattice[count]
+    int4 *tiles = nullptr;           // device tile list (capacity max_tiles)
+    int *ntiles = nullptr;           // device tile count
+    size_t max_tiles = 0;
+    // observables
+    int4 *sblocks = nullptr;
+    int2 *ranges = nullptr;
+    int *ids = nullptr;
+    double *partial = nullptr, *out = nullptr;
+    size_t max_sblocks = 0;
+    // launch
+    int tx = 128, groups = 0, flags = pplbm::kFlagShallow;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+    bool tiles_dirty = true;
+    std::string err;
+};
+
+namespace {
+
+int bfail(lbm_batch *b, int code, const std::string &m) {
+    if (b) b->err = m;
+    return code;
+}
+
+#define BHIP(b, call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) return bfail(b, LBM_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t tiles_of(const lbm_batch *b, int i) {
+    const Physics &p = b->phys[i];
+    return (size_t)((p.nx + b->tx - 1) / b->tx) * ((p.ny + b->seg_rows[i] - 1) / b->seg_rows[i]);
+}
+
+int upload_desc(lbm_batch *b) {
+    const size_t sz = pplbm::batch_lattice_bytes();
+    std::vector<char> host(sz * b->count);
+    for (int i = 0; i < b->count; ++i)
+        pplbm::batch_lattice_fill(b->phys[i], b->f0[i], b->f1[i], b->vprev[i], b->xa[i], b->ya[i],
+                                  b->xb[i], b->yb[i], b->flags & pplbm::kFlagNT, host.data() + i * sz);
+    BHIP(b, hipMemcpyAsync(b->desc, host.data(), host.size(), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+// Tile list of the active lattices (strips of tx columns x segments of seg_rows rows).
+int upload_tiles(lbm_batch *b) {
+    size_t need = 0;
+    for (int i = 0; i < b->count; ++i) need += tiles_of(b, i);
+    if (need > b->max_tiles) {
+        if (b->tiles) (void)hipFree(b->tiles);
+        b->tiles = nullptr;
+        if (hipMalloc(&b->tiles, need * sizeof(int4)) != hipSuccess) {
+            (void)hipGetLastError();
+            return bfail(b, LBM_ENOMEM, "tile list allocation failed");
+        }
+        b->max_tiles = need;
+        if (b->graph) {  // the captured graph holds the old tile list pointer
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
+    }
+    std::vector<int4> t;
+    t.reserve(need);
+    for (int i = 0; i < b->count; ++i) {
+        if (!b->active[i]) continue;
+        const Physics &p = b->phys[i];
+        const int H = b->seg_rows[i];
+        for (int y0 = 0; y0 < p.ny; y0 += H)
+            for (int x0 = 0; x0 < p.nx; x0 += b->tx) t.push_back(make_int4(i, x0, y0, H));
+    }
+    const int n = (int)t.size();
+    if (n) BHIP(b, hipMemcpyAsync(b->tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->ntiles, &n, sizeof n, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->tiles_dirty = false;
+    return LBM_OK;
+}
+
+int grid_groups(const lbm_batch *b) {
+    if (b->groups > 0) return b->groups;
+    size_t all = 0;
+    for (int i = 0; i < b->count; ++i) all += tiles_of(b, i);
+    const size_t g = std::min<size_t>(all, 2048);  // ~8 workgroups per compute unit
+    return (int)std::max<size_t>(g, 1);
+}
+
+int launch_steps(lbm_batch *b, int n) {
+    for (int k = 0; k < n; ++k)
+        BHIP(b, pplbm::launch_batch_sweep(b->desc, b->tiles, b->ntiles, k & 1, b->tx, grid_groups(b),
+                                          b->flags & pplbm::kFlagShallow, b->stream));
+    return LBM_OK;
+}
+
+int ensure_graph(lbm_batch *b, int steps) {
+    if (b->graph && b->graph_steps == steps) return LBM_OK;
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_steps(b, steps);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    b->graph_steps = steps;
+    return LBM_OK;
+}
+
+bool any_active(const lbm_batch *b) {
+    for (int i = 0; i < b->count; ++i)
+        if (b->active[i]) return true;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos,
+                     const lbm_force *force, const lbm_collision *coll, const double *tau,
+                     lbm_batch_t **out) {
+    if (!out || count < 1 || !nx || !ny || !eos || !force || !coll || !tau) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ENOMEM;
+    b->count = count;
+    b->phys.resize(count);
+    for (int i = 0; i < count; ++i) {
+        std::string why;
+        int rc = pplbm::make_physics(nx[i], ny[i], &eos[i], &force[i], &coll[i], tau[i], &b->phys[i],
+                                     nullptr, &why);
+        if (rc) {
+            delete b;
+            return rc;
+        }
+    }
+    b->f0.assign(count, nullptr);
+    b->f1.assign(count, nullptr);
+    b->vprev.assign(count, nullptr);
+    b->seg_rows.assign(count, 32);
+    b->active.assign(count, 0);
+    b->initialised.assign(count, 0);
+    b->steps.assign(count, 0);
+    b->vprev_valid.assign(count, 0);
+    b->xa.resize(count);
+    b->ya.resize(count);
+    b->xb.assign(count, 0);
+    b->yb.assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        b->xa[i] = nx[i] / 2;
+        b->ya[i] = ny[i] / 2;
+    }
+    bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < count; ++i) {
+        const Physics &p = b->phys[i];
+        const size_t fb = 9 * p.plane * sizeof(float), vb = 2 * (size_t)p.nx * p.ny * sizeof(float);
+        ok = hipMalloc(&b->f0[i], fb) == hipSuccess && hipMalloc(&b->f1[i], fb) == hipSuccess &&
+             hipMalloc(&b->vprev[i], vb) == hipSuccess;
+        ok = ok && hipMemsetAsync(b->f0[i], 0, fb, b->stream) == hipSuccess &&
+             hipMemsetAsync(b->f1[i], 0, fb, b->stream) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&b->desc, pplbm::batch_lattice_bytes() * count) == hipSuccess &&
+         hipMalloc(&b->ntiles, sizeof(int)) == hipSuccess &&
+         hipMalloc(&b->out, pplbm::kStatsOut * sizeof(double) * count) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        lbm_batch_destroy(b);
+        return LBM_ENOMEM;
+    }
+    if (upload_desc(b) || upload_tiles(b)) {
+        lbm_batch_destroy(b);
+        return LBM_EHIP;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch_t *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (int i = 0; i < b->count; ++i) {
+        if (b->f0[i]) (void)hipFree(b->f0[i]);
+        if (b->f1[i]) (void)hipFree(b->f1[i]);
+        if (b->vprev[i]) (void)hipFree(b->vprev[i]);
+    }
+    for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->ntiles, (void *)b->sblocks,
+                    (void *)b->ranges, (void *)b->ids, (void *)b->partial, (void *)b->out})
+        if (p) (void)hipFree(p);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags) {
+    if (!b) return LBM_EINVAL;
+    if (tx < 64 || tx % 64 || tx > 512 || groups < 0)
+        return bfail(b, LBM_EINVAL, "tx: multiple of 64 up to 512; groups >= 0 (0 = automatic)");
+    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW))
+        return bfail(b, LBM_EINVAL, "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW");
+    b->tx = tx;
+    b->groups = groups;
+    b->flags = flags;
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    int rc = upload_desc(b);
+    return rc ? rc : upload_tiles(b);
+}
+
+int lbm_batch_set_segment(lbm_batch_t *b, int i, int rows) {
+    if (!b || i < 0 || i >= b->count || rows < 1) return LBM_EINVAL;
+    b->seg_rows[i] = rows;
+    return upload_tiles(b);
+}
+
+int lbm_batch_set_active(lbm_batch_t *b, int i, int active) {
+    if (!b || i < 0 || i >= b->count) return LBM_EINVAL;
+    if (active && !b->initialised[i]) return bfail(b, LBM_ESTATE, "lattice not initialised");
+    b->active[i] = active != 0;
+    return upload_tiles(b);
+}
+
+int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0) {
+    if (!b || i < 0 || i >= b->count || !rho0) return LBM_EINVAL;
+    const Physics &p = b->phys[i];
+    const size_t N = (size_t)p.nx * p.ny;
+    for (size_t k = 0; k < N; ++k)
+        if (!(rho0[k] > 0) || !(p.b_quarter * rho0[k] < 1))
+            return bfail(b, LBM_EUNSTABLE, "initial density outside (0, 4/b)");
+    double *d = nullptr;
+    if (hipMalloc(&d, N * sizeof(double) * (u0 ? 3 : 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, LBM_ENOMEM, "staging allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(d, rho0, N * sizeof(double), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && u0)
+        e = hipMemcpyAsync(d + N, u0, 2 * N * sizeof(double), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = pplbm::launch_init(p, d, u0 ? d + N : nullptr, b->f0[i], b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("lbm_batch_init: ") + hipGetErrorString(e));
+    b->initialised[i] = 1;
+    b->active[i] = 1;
+    b->steps[i] = 0;
+    b->vprev_valid[i] = 0;
+    return upload_tiles(b);
+}
+
+int lbm_batch_step(lbm_batch_t *b, int n) {
+    if (!b || n < 0 || n % 2) return bfail(b, LBM_EINVAL, "lbm_batch_step: n must be even and >= 0");
+    if (b->tiles_dirty) {
+        int rc = upload_tiles(b);
+        if (rc) return rc;
+    }
+    if (!n || !any_active(b)) return LBM_OK;
+    int rc = ensure_graph(b, n);
+    if (rc) return rc;
+    BHIP(b, hipGraphLaunch(b->graph, b->stream));
+    for (int i = 0; i < b->count; ++i)
+        if (b->active[i]) b->steps[i] += n;
+    return LBM_OK;
+}
+
+// FP64 observables of every active lattice (out[i] for active i; others untouched).
+int lbm_batch_stats(lbm_batch_t *b, int track_dv, lbm_stats_t *out) {
+    if (!b || !out) return LBM_EINVAL;
+    std::vector<int4> sb;
+    std::vector<int2> ranges;
+    std::vector<int> ids;
+    for (int i = 0; i < b->count; ++i) {
+        if (!b->active[i]) continue;
+        const Physics &p = b->phys[i];
+        const size_t N = (size_t)p.nx * p.ny;
+        const int chunks = (int)std::min<size_t>((N + 255) / 256, 64);
+        ranges.push_back(make_int2((int)sb.size(), chunks));
+        ids.push_back(i);
+        for (int c = 0; c < chunks; ++c) sb.push_back(make_int4(i, c, chunks, (int)sb.size()));
+    }
+    if (ids.empty()) return LBM_OK;
+    if (sb.size() > b->max_sblocks) {
+        for (void *p : {(void *)b->sblocks, (void *)b->ranges, (void *)b->ids, (void *)b->partial})
+            if (p) (void)hipFree(p);
+        b->sblocks = nullptr;
+        b->ranges = nullptr;
+        b->ids = nullptr;
+        b->partial = nullptr;
+        const size_t m = sb.size();
+        if (hipMalloc(&b->sblocks, m * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&b->ranges, b->count * sizeof(int2)) != hipSuccess ||
+            hipMalloc(&b->ids, b->count * sizeof(int)) != hipSuccess ||
+            hipMalloc(&b->partial, m * pplbm::kStatsFields * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            b->max_sblocks = 0;
+            return bfail(b, LBM_ENOMEM, "reduction buffers");
+        }
+        b->max_sblocks = m;
+    }
+    BHIP(b, hipMemcpyAsync(b->sblocks, sb.data(), sb.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->ranges, ranges.data(), ranges.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, pplbm::launch_batch_stats(b->desc, b->sblocks, (int)sb.size(), b->ranges, b->ids,
+                                      (int)ids.size(), 0, track_dv, b->partial, b->out, b->stream));
+    std::vector<double> r(pplbm::kStatsOut * b->count);
+    BHIP(b, hipMemcpyAsync(r.data(), b->out, r.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    int unstable = 0;
+    for (int i : ids) {
+        const double *q = &r[(size_t)i * pplbm::kStatsOut];
+        lbm_stats_t &s = out[i];
+        s.mass = q[0];
+        s.rho_min = q[1];
+        s.rho_max = q[2];
+        s.us_max = q[3];
+        s.dv_max = (track_dv && b->vprev_valid[i]) ? q[4] : 0.0;
+        s.nonfinite = (int)q[5];
+        s.rho_probe_a = q[6];
+        s.rho_probe_b = q[7];
+        s.ratio = std::fmax(q[6], q[7]) / std::fmin(q[6], q[7]);
+        s.step = b->steps[i];
+        if (track_dv) b->vprev_valid[i] = 1;
+        if (s.nonfinite) unstable = 1;
+    }
+    return unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int lbm_batch_run(lbm_batch_t *b, double tol, int check_every, long long max_steps,
+                  long long *steps_out, int *status_out) {
+    if (!b || !(tol > 0) || check_every < 2 || check_every % 2 || max_steps < 0)
+        return bfail(b, LBM_EINVAL, "lbm_batch_run: tol > 0, even check_every >= 2");
+    std::vector<lbm_stats_t> st(b->count);
+    for (int i = 0; i < b->count; ++i)
+        if (status_out) status_out[i] = b->active[i] ? LBM_ENOTCONVERGED : LBM_ESTATE;
+    int rc = lbm_batch_stats(b, 1, st.data());  // first velocity snapshot
+    if (rc && rc != LBM_EUNSTABLE) return rc;
+    while (any_active(b)) {
+        rc = lbm_batch_step(b, check_every);
+        if (rc) return rc;
+        rc = lbm_batch_stats(b, 1, st.data());
+        if (rc && rc != LBM_EUNSTABLE) return rc;
+        bool changed = false;
+        for (int i = 0; i < b->count; ++i) {
+            if (!b->active[i]) continue;
+            int status = 1;  // still running
+            if (st[i].nonfinite) status = LBM_EUNSTABLE;
+            else if (st[i].dv_max / check_every < tol) status = LBM_OK;
+            else if (b->steps[i] >= max_steps) status = LBM_ENOTCONVERGED;
+            if (status != 1) {
+                b->active[i] = 0;
+                changed = true;
+                if (status_out) status_out[i] = status;
+            }
+        }
+        if (changed) {
+            rc = upload_tiles(b);
+            if (rc) return rc;
+        }
+    }
+    if (steps_out)
+        for (int i = 0; i < b->count; ++i) steps_out[i] = b->steps[i];
+    return LBM_OK;
+}
+
+int lbm_batch_read(lbm_batch_t *b, int i, double *rho, double *u) {
+    if (!b || i < 0 || i >= b->count) return LBM_EINVAL;
+    if (!b->initialised[i]) return bfail(b, LBM_ESTATE, "lattice not initialised");
+    const Physics &p = b->phys[i];
+    const size_t N = (size_t)p.nx * p.ny;
+    double *d = nullptr;
+    float *psi = nullptr;
+    if (hipMalloc(&d, 3 * N * sizeof(double)) != hipSuccess || hipMalloc(&psi, p.plane * sizeof(float)) != hipSuccess) {
+        if (d) (void)hipFree(d);
+        (void)hipGetLastError();
+        return bfail(b, LBM_ENOMEM, "staging allocation failed");
+    }
+    hipError_t e = pplbm::launch_psi(p, pplbm::kPrecF64, 0, b->f0[i], psi, b->stream);
+    if (e == hipSuccess) e = pplbm::launch_macro(p, b->f0[i], psi, d, d + N, b->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, N * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + N, 2 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(d);
+    (void)hipFree(psi);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("lbm_batch_read: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_batch_populations(lbm_batch_t *b, int i, float *f) {
+    if (!b || i < 0 || i >= b->count || !f) return LBM_EINVAL;
+    const Physics &p = b->phys[i];
+    for (int q = 0; q < 9; ++q)
+        BHIP(b, hipMemcpy2DAsync(f + (size_t)q * p.nx * p.ny, p.nx * sizeof(float), b->f0[i] + q * p.fq,
+                                 p.frow * sizeof(float), p.nx * sizeof(float), p.ny, hipMemcpyDeviceToHost,
+                                 b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+long long lbm_batch_steps(const lbm_batch_t *b, int i) {
+    if (!b || i < 0 || i >= b->count) return -1;
+    return b->steps[i];
+}
+
+int lbm_batch_sync(lbm_batch_t *b) {
+    if (!b) return LBM_EINVAL;
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch_t *b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
+
+#include "../../include/pplbm.h"
 
 namespace pplbm {
 
@@ -44,6 +47,11 @@ struct Launch {
     int flags = 0;
 };
 
+// Validated physics of one lattice (rows layout); T_out receives the absolute temperature.
+int make_physics(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
+                 const lbm_collision *collision, double tau, Physics *out, double *T_out,
+                 std::string *why);
+
 // Density / psi pass (Eq. 3, Eq. 29-30, Eq. 7): psi[y * pitch + x] from f.
 hipError_t launch_psi(const Physics &p, int prec, int flags, const float *f, float *psi,
                       hipStream_t stream);
@@ -76,5 +84,22 @@ hipError_t launch_stats(const Physics &p, const float *f, const float *psi, floa
                         hipStream_t stream);
 
 hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t stream);
+
+// ---- batched sweep ----------------------------------------------------------------------
+// Device descriptor of one batch lattice (opaque to the runtime; filled on the host).
+size_t batch_lattice_bytes();
+void batch_lattice_fill(const Physics &p, float *f0, float *f1, float *vprev, int xa, int ya,
+                        int xb, int yb, int flags, void *out);
+// One step of every lattice in the tile list: tiles[t] = (lattice, x0, y0, rows), *ntiles
+// entries, read from f[parity], written to f[parity ^ 1].  tx threads per workgroup, `groups`
+// persistent workgroups.
+hipError_t launch_batch_sweep(const void *lats, const int4 *tiles, const int *ntiles, int parity,
+                              int tx, int groups, bool shallow, hipStream_t stream);
+// Observables of the lattices listed in ids (nlat of them) from f[parity]: sblocks[b] =
+// (lattice, chunk, chunks, partial slot); ranges[i] = (first partial, count) of ids[i]; out
+// receives kStatsOut doubles per lattice id.
+hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblocks,
+                              const int2 *ranges, const int *ids, int nlat, int parity, int track,
+                              double *partial, double *out, hipStream_t stream);
 
 }  // namespace pplbm

@@ -401,16 +401,14 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
 // collided, row y+1 (loaded one iteration earlier) becomes psi and the loads of row y+2 are
 // in flight.  Same per-node arithmetic as the two-pass step, bit for bit.
 // ---------------------------------------------------------------------------------------
+// One tile of the sweep: columns [x0, x0 + blockDim.x) (clipped at nx) and rows [y0, y0 + H)
+// (clipped at ny) of the lattice described by c; ring is the workgroup's LDS (4 x (TX + 2)).
 template <typename R, typename D, int SCHEME, int COLL, int PF>
-__global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
-                                                    float *__restrict__ fout,
-                                                    StepConst<R, D> c, int H) {
-    extern __shared__ float ring[];  // 4 rows x (TX + 2)
+__device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float *__restrict__ fout,
+                                           const StepConst<R, D> &c, int x0, int y0, int H,
+                                           float *ring) {
     const int TX = blockDim.x, W = TX + 2;
     const int nx = c.nx, ny = c.ny;
-    const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
-                          c.flags & kFlagXCD);
-    const int x0 = (b % gridDim.x) * TX, y0 = (b / gridDim.x) * H;
     const int tx = threadIdx.x;
     const int na = nx - x0 < TX ? nx - x0 : TX;  // active columns of this strip
     const bool active = tx < na;
@@ -484,6 +482,106 @@ __global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fi
             fa[q] = fb[q];
             if (PF == 2) fb[q] = fc[q];
         }
+    }
+}
+
+template <typename R, typename D, int SCHEME, int COLL, int PF>
+__global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
+                                                    float *__restrict__ fout,
+                                                    StepConst<R, D> c, int H) {
+    extern __shared__ float ring[];  // 4 rows x (TX + 2)
+    const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
+                          c.flags & kFlagXCD);
+    sweep_tile<R, D, SCHEME, COLL, PF>(fin, fout, c, (b % gridDim.x) * blockDim.x,
+                                       (b / gridDim.x) * H, H, ring);
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched sweep: many independent lattices (own size, physics and relaxation) advanced by one
+// launch per step.  Each workgroup walks the shared tile list (lattice, x0, y0, rows) with a
+// stride of the grid size; the list and its length live in device memory, so the host can
+// drop converged lattices between replays of a captured graph.  Mixed precision.
+// ---------------------------------------------------------------------------------------
+struct BatchLattice {
+    StepConst<float, double> c;
+    float *f[2];
+    float *vprev;            // velocity at the previous convergence check (2 floats per node)
+    int scheme, coll;
+    int xa, ya, xb, yb;      // probe nodes
+};
+
+template <int PF>
+__global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchLattice *__restrict__ lats,
+                                                          const int4 *__restrict__ tiles,
+                                                          const int *__restrict__ ntiles,
+                                                          int parity) {
+    extern __shared__ float ring[];
+    const int n = *ntiles;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BatchLattice &L = lats[tl.x];
+        const StepConst<float, double> c = L.c;
+        const float *fin = L.f[parity];
+        float *fout = L.f[parity ^ 1];
+        switch (L.scheme * 2 + L.coll) {
+        case EDM * 2 + BGK:
+            sweep_tile<float, double, EDM, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
+        case GUO * 2 + BGK:
+            sweep_tile<float, double, GUO, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
+        case GUO_LI * 2 + BGK:
+            sweep_tile<float, double, GUO_LI, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
+        case GUO * 2 + MRT:
+            sweep_tile<float, double, GUO, MRT, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
+        default:
+            sweep_tile<float, double, GUO_LI, MRT, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
+        }
+        __syncthreads();  // the ring is reused by the next tile
+    }
+}
+
+// FP64 observables of one node of a batch lattice; psi of the stencil recomputed from f.
+__device__ __forceinline__ void batch_node(const BatchLattice &L, const float *__restrict__ f,
+                                           int x, int y, double acc[6], size_t k, bool track) {
+    const StepConst<float, double> &c = L.c;
+    const int xe = x + 1 == c.nx ? 0 : x + 1, xw = x == 0 ? c.nx - 1 : x - 1;
+    const int yn = y + 1 == c.ny ? 0 : y + 1, ys = y == 0 ? c.ny - 1 : y - 1;
+    float v[9];
+    auto P = [&](int xx, int yy) {
+        float w[9];
+        load9(f, (size_t)yy * c.frow + xx, c.fq, w);
+        return (double)c.psi_of(w);
+    };
+    load9(f, (size_t)y * c.frow + x, c.fq, v);
+    const double rho = density9<double>(v);
+    const double jx = (((double)v[1] - v[3]) + ((double)v[5] - v[7])) + ((double)v[8] - v[6]);
+    const double jy = (((double)v[2] - v[4]) + ((double)v[5] - v[7])) + ((double)v[6] - v[8]);
+    const double pc = c.psi_of(v), pE = P(xe, y), pW = P(xw, y), pN = P(x, yn), pS = P(x, ys);
+    const double pNE = P(xe, yn), pNW = P(xw, yn), pSW = P(xw, ys), pSE = P(xe, ys);
+    const double dA = pNE - pSW, dB = pSE - pNW;
+    const double s1x = (pE - pW) / 3.0 + (dA + dB) / 12.0;
+    const double s1y = (pN - pS) / 3.0 + (dA - dB) / 12.0;
+    const double qA = dA * (pNE + pSW), qB = dB * (pSE + pNW);
+    const double s2x = (pE - pW) * (pE + pW) / 3.0 + (qA + qB) / 12.0;
+    const double s2y = (pN - pS) * (pN + pS) / 3.0 + (qA - qB) / 12.0;
+    const double Fx = c.gB * pc * s1x + c.gA * s2x, Fy = c.gB * pc * s1y + c.gA * s2y;
+    const double vx = jx / rho + Fx / (2.0 * rho), vy = jy / rho + Fy / (2.0 * rho);
+    if (!(isfinite(rho) && isfinite(vx) && isfinite(vy) && isfinite(pc))) {
+        acc[5] += 1.0;
+        return;
+    }
+    acc[0] += rho;
+    acc[1] = fmin(acc[1], rho);
+    acc[2] = fmax(acc[2], rho);
+    acc[3] = fmax(acc[3], sqrt(vx * vx + vy * vy));
+    if (track) {
+        acc[4] = fmax(acc[4], fmax(fabs(vx - (double)L.vprev[2 * k]), fabs(vy - (double)L.vprev[2 * k + 1])));
+        L.vprev[2 * k] = (float)vx;
+        L.vprev[2 * k + 1] = (float)vy;
     }
 }
 
@@ -632,6 +730,57 @@ __global__ void __launch_bounds__(kStatsBlock) stats_final_kernel(Physics p, con
         float v[9];
         load9(f, (size_t)y * p.frow + x, p.fq, v);
         out[kStatsFields + threadIdx.x] = density9<double>(v);
+    }
+}
+
+// Batch observables.  Block b covers chunk sb[b].y of sb[b].z chunks of lattice sb[b].x and
+// writes its partial at sb[b].w; one final block per lattice reduces its chunks in order.
+__global__ void __launch_bounds__(kStatsBlock) batch_stats_kernel(const BatchLattice *__restrict__ lats,
+                                                                  const int4 *__restrict__ sb, int parity,
+                                                                  int track, double *__restrict__ partial) {
+    __shared__ double sh[kStatsFields][kStatsBlock];
+    double acc[kStatsFields] = {0.0, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
+    const int4 d = sb[blockIdx.x];
+    const BatchLattice &L = lats[d.x];
+    const float *f = L.f[parity];
+    const size_t N = (size_t)L.c.nx * L.c.ny;
+    const size_t stride = (size_t)d.z * kStatsBlock;
+    for (size_t k = (size_t)d.y * kStatsBlock + threadIdx.x; k < N; k += stride) {
+        const int y = (int)(k / L.c.nx), x = (int)(k - (size_t)y * L.c.nx);
+        batch_node(L, f, x, y, acc, k, track != 0);
+    }
+    block_reduce(acc, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kStatsFields; ++q) partial[(size_t)d.w * kStatsFields + q] = sh[q][0];
+}
+
+__global__ void __launch_bounds__(kStatsBlock) batch_stats_final_kernel(const BatchLattice *__restrict__ lats,
+                                                                        const int2 *__restrict__ ranges,
+                                                                        const int *__restrict__ ids,
+                                                                        int parity, const double *__restrict__ partial,
+                                                                        double *__restrict__ out) {
+    __shared__ double sh[kStatsFields][kStatsBlock];
+    double acc[kStatsFields] = {0.0, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
+    const int2 r = ranges[blockIdx.x];  // first partial, count
+    for (int b = threadIdx.x; b < r.y; b += kStatsBlock) {
+        const double *q = partial + (size_t)(r.x + b) * kStatsFields;
+        acc[0] += q[0];
+        acc[1] = fmin(acc[1], q[1]);
+        acc[2] = fmax(acc[2], q[2]);
+        acc[3] = fmax(acc[3], q[3]);
+        acc[4] = fmax(acc[4], q[4]);
+        acc[5] += q[5];
+    }
+    block_reduce(acc, sh);
+    const int id = ids[blockIdx.x];
+    double *o = out + (size_t)id * kStatsOut;
+    if (threadIdx.x < kStatsFields) o[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 0 || threadIdx.x == 1) {
+        const BatchLattice &L = lats[id];
+        const int x = threadIdx.x == 0 ? L.xa : L.xb, y = threadIdx.x == 0 ? L.ya : L.yb;
+        float v[9];
+        load9(L.f[parity], (size_t)y * L.c.frow + x, L.c.fq, v);
+        o[kStatsFields + threadIdx.x] = density9<double>(v);
     }
 }
 
@@ -796,6 +945,48 @@ hipError_t launch_stats(const Physics &p, const float *f, const float *psi, floa
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kStatsBlock), 0, s, p, f, partial, nb, out,
                        xa, ya, xb, yb);
+    return hipGetLastError();
+}
+
+size_t batch_lattice_bytes() { return sizeof(BatchLattice); }
+
+void batch_lattice_fill(const Physics &p, float *f0, float *f1, float *vprev, int xa, int ya,
+                        int xb, int yb, int flags, void *out) {
+    BatchLattice L{};
+    L.c = make_const<float, double>(p, flags);
+    L.f[0] = f0;
+    L.f[1] = f1;
+    L.vprev = vprev;
+    L.scheme = p.scheme;
+    L.coll = p.coll;
+    L.xa = xa;
+    L.ya = ya;
+    L.xb = xb;
+    L.yb = yb;
+    *reinterpret_cast<BatchLattice *>(out) = L;
+}
+
+hipError_t launch_batch_sweep(const void *lats, const int4 *tiles, const int *ntiles, int parity,
+                              int tx, int groups, bool shallow, hipStream_t s) {
+    const size_t lds = 4 * (size_t)(tx + 2) * sizeof(float);
+    const BatchLattice *L = reinterpret_cast<const BatchLattice *>(lats);
+    if (shallow)
+        hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3(groups), dim3(tx), lds, s, L, tiles, ntiles, parity);
+    else
+        hipLaunchKernelGGL(batch_sweep_kernel<2>, dim3(groups), dim3(tx), lds, s, L, tiles, ntiles, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblocks,
+                              const int2 *ranges, const int *ids, int nlat, int parity, int track,
+                              double *partial, double *out, hipStream_t s) {
+    const BatchLattice *L = reinterpret_cast<const BatchLattice *>(lats);
+    hipLaunchKernelGGL(batch_stats_kernel, dim3(nsblocks), dim3(kStatsBlock), 0, s, L, sblocks, parity,
+                       track, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_stats_final_kernel, dim3(nlat), dim3(kStatsBlock), 0, s, L, ranges, ids,
+                       parity, partial, out);
     return hipGetLastError();
 }
 

@@ -231,3 +231,115 @@ class Lattice:
         a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
         check(lbm_timing(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), self.h)
         return a.value, b.value, n.value
+
+
+# ---- batched sweep -------------------------------------------------------------------------
+_BSIG = {
+    "lbm_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(lbm_eos),
+                                        ctypes.POINTER(lbm_force), ctypes.POINTER(lbm_collision),
+                                        _D, ctypes.POINTER(_P)]),
+    "lbm_batch_destroy": (None, [_P]),
+    "lbm_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lbm_batch_set_segment": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "lbm_batch_init": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+    "lbm_batch_set_active": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbm_batch_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
+    "lbm_batch_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_longlong,
+                                     ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]),
+    "lbm_batch_read": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+    "lbm_batch_populations": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_batch_steps": (ctypes.c_longlong, [_P, ctypes.c_int]),
+    "lbm_batch_sync": (ctypes.c_int, [_P]),
+    "lbm_batch_last_error": (ctypes.c_char_p, [_P]),
+}
+for _name, (_res, _args) in _BSIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+def bcheck(code, b=None):
+    if code != LBM_OK:
+        raise LBMError(code, lbm_batch_last_error(b).decode() if b else "")
+    return code
+
+
+class Batch:
+    """Independent lattices advanced together (lbm_batch_*).  members: list of dicts with nx,
+    ny, T_over_Tc, K, scheme, A, sigma, collision, s (5 MRT rates), tau."""
+
+    def __init__(self, members, tx=128, groups=0, flags=LBM_LAUNCH_SHALLOW):
+        n = len(members)
+        self.members = members
+        nx = (ctypes.c_int * n)(*[m["nx"] for m in members])
+        ny = (ctypes.c_int * n)(*[m["ny"] for m in members])
+        eos = (lbm_eos * n)(*[make_eos(m["T_over_Tc"], K=m.get("K", 1.0)) for m in members])
+        frc = (lbm_force * n)(*[make_force(m.get("scheme", "GUO"), A=m.get("A", 0.0),
+                                           sigma=m.get("sigma", 0.0)) for m in members])
+        col = (lbm_collision * n)(*[make_collision(m.get("collision", "BGK"),
+                                                   s=m.get("s", (1.0, 1.1, 1.1, 1.0, 1.1)))
+                                    for m in members])
+        tau = (ctypes.c_double * n)(*[m["tau"] for m in members])
+        b = _P()
+        check(lbm_batch_create(n, nx, ny, eos, frc, col, tau, ctypes.byref(b)))
+        self.b = b
+        bcheck(lbm_batch_set_launch(b, tx, groups, flags), b)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            lbm_batch_destroy(b)
+            self.b = None
+
+    def set_segment(self, i, rows):
+        bcheck(lbm_batch_set_segment(self.b, i, rows), self.b)
+
+    def init(self, i, rho0, u0=None):
+        m = self.members[i]
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert rho0.shape == (m["ny"], m["nx"])
+        u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+        bcheck(lbm_batch_init(self.b, i, _dptr(rho0), _dptr(u0)), self.b)
+
+    def set_active(self, i, on):
+        bcheck(lbm_batch_set_active(self.b, i, int(on)), self.b)
+
+    def step(self, n):
+        bcheck(lbm_batch_step(self.b, int(n)), self.b)
+
+    def sync(self):
+        bcheck(lbm_batch_sync(self.b), self.b)
+
+    def stats(self, track_dv=False, allow_unstable=True):
+        out = (lbm_stats_t * len(self.members))()
+        rc = lbm_batch_stats(self.b, int(track_dv), out)
+        if rc != LBM_OK and not (allow_unstable and rc == LBM_EUNSTABLE):
+            bcheck(rc, self.b)
+        return [s.as_dict() for s in out]
+
+    def run(self, tol, check_every=100, max_steps=2_000_000):
+        n = len(self.members)
+        steps = (ctypes.c_longlong * n)()
+        status = (ctypes.c_int * n)()
+        bcheck(lbm_batch_run(self.b, tol, check_every, max_steps, steps, status), self.b)
+        return list(steps), list(status)
+
+    def read(self, i):
+        m = self.members[i]
+        rho = np.empty((m["ny"], m["nx"]))
+        u = np.empty((m["ny"], m["nx"], 2))
+        bcheck(lbm_batch_read(self.b, i, _dptr(rho), _dptr(u)), self.b)
+        return rho, u
+
+    def populations(self, i):
+        m = self.members[i]
+        f = np.empty((9, m["ny"], m["nx"]), dtype=np.float32)
+        bcheck(lbm_batch_populations(self.b, i, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               self.b)
+        return f
+
+    def steps(self, i):
+        return int(lbm_batch_steps(self.b, i))
