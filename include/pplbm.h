@@ -238,12 +238,13 @@ int lbm_batch_step(lbm_batch_t *b, int n);
  * lbm_stats.  Synchronises.  LBM_EUNSTABLE if any lattice has non-finite nodes. */
 int lbm_batch_stats(lbm_batch_t *b, int track_dv, lbm_stats_t *out);
 
-/* Step every active lattice until max_x |v(t) - v(t - check_every)|_inf / check_every < tol
- * (converged, status 0), a node goes non-finite (LBM_EUNSTABLE) or max_steps is reached
- * (LBM_ENOTCONVERGED); check_every even.  steps_out / status_out: count entries (either may be
- * NULL).  Lattices already inactive keep status LBM_ESTATE. */
-int lbm_batch_run(lbm_batch_t *b, double tol, int check_every, long long max_steps,
-                  long long *steps_out, int *status_out);
+/* Step every active lattice until it has converged (status 0) -- max_x |v(t) - v(t - k)|_inf / k
+ * < tol and, if tol_rho > 0, the relative change of both probe densities over the last k steps,
+ * divided by k, < tol_rho (k = check_every, even) -- or a node goes non-finite (LBM_EUNSTABLE)
+ * or max_steps is reached (LBM_ENOTCONVERGED).  steps_out / status_out: count entries (either
+ * may be NULL).  Lattices already inactive keep status LBM_ESTATE. */
+int lbm_batch_run(lbm_batch_t *b, double tol, double tol_rho, int check_every,
+                  long long max_steps, long long *steps_out, int *status_out);
 
 /* rho and v of lattice i (as lbm_read); its populations as FP32 [9][ny][nx]. */
 int lbm_batch_read(lbm_batch_t *b, int i, double *rho, double *u);
@@ -253,6 +254,31 @@ int lbm_batch_populations(lbm_batch_t *b, int i, float *f);
 long long lbm_batch_steps(const lbm_batch_t *b, int i);
 int lbm_batch_sync(lbm_batch_t *b);
 const char *lbm_batch_last_error(const lbm_batch_t *b);
+
+/* ---- learned warm start: multilayer perceptron ---------------------------------------------
+ * Dense layers dims[0] -> dims[1] -> ... -> dims[nlayers], tanh on every hidden layer, linear
+ * output, FP32 on the GPU; trained with mean-squared error and Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8).  Parameters are one flat FP32 vector: for each layer l, W_l (row-major
+ * [dims[l+1]][dims[l]]) then b_l.  x, y, target, dy and grad are device pointers (row-major
+ * [batch][dim]); `stream` is a hipStream_t (NULL = default).  Used to predict a droplet's
+ * radial density profile from (T/Tc, tau, R, K) as the initial state of the batched sweep. */
+typedef struct lbm_mlp lbm_mlp_t;
+int lbm_mlp_create(int nlayers, const int *dims, lbm_mlp_t **out);
+void lbm_mlp_destroy(lbm_mlp_t *n);
+size_t lbm_mlp_param_count(const lbm_mlp_t *n);
+/* Host FP32 parameter vector in / out; setting it also resets the Adam state. */
+int lbm_mlp_set_params(lbm_mlp_t *n, const float *host_params);
+int lbm_mlp_get_params(lbm_mlp_t *n, float *host_params);
+/* y = net(x). */
+int lbm_mlp_forward(lbm_mlp_t *n, const float *x, int batch, float *y, void *stream);
+/* grad = d(sum_b sum_o dy[b][o] y[b][o]) / d(parameters) at x (one forward + backward pass). */
+int lbm_mlp_gradient(lbm_mlp_t *n, const float *x, const float *dy, int batch, float *grad,
+                     void *stream);
+/* One Adam step on the mean-squared error mean((net(x) - target)^2) with learning rate lr;
+ * *loss_out (may be NULL) receives the loss before the step (synchronises when given). */
+int lbm_mlp_train_step(lbm_mlp_t *n, const float *x, const float *target, int batch, float lr,
+                       float *loss_out, void *stream);
+const char *lbm_mlp_last_error(const lbm_mlp_t *n);
 
 /* ---- EOS helpers (host only) -------------------------------------------------------------- */
 

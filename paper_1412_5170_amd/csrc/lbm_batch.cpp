@@ -369,15 +369,20 @@ int lbm_batch_stats(lbm_batch_t *b, int track_dv, lbm_stats_t *out) {
     return unstable ? LBM_EUNSTABLE : LBM_OK;
 }
 
-int lbm_batch_run(lbm_batch_t *b, double tol, int check_every, long long max_steps,
-                  long long *steps_out, int *status_out) {
+int lbm_batch_run(lbm_batch_t *b, double tol, double tol_rho, int check_every,
+                  long long max_steps, long long *steps_out, int *status_out) {
     if (!b || !(tol > 0) || check_every < 2 || check_every % 2 || max_steps < 0)
         return bfail(b, LBM_EINVAL, "lbm_batch_run: tol > 0, even check_every >= 2");
     std::vector<lbm_stats_t> st(b->count);
+    std::vector<double> pa(b->count, 0.0), pb(b->count, 0.0);
     for (int i = 0; i < b->count; ++i)
         if (status_out) status_out[i] = b->active[i] ? LBM_ENOTCONVERGED : LBM_ESTATE;
     int rc = lbm_batch_stats(b, 1, st.data());  // first velocity snapshot
     if (rc && rc != LBM_EUNSTABLE) return rc;
+    for (int i = 0; i < b->count; ++i) {
+        pa[i] = st[i].rho_probe_a;
+        pb[i] = st[i].rho_probe_b;
+    }
     while (any_active(b)) {
         rc = lbm_batch_step(b, check_every);
         if (rc) return rc;
@@ -386,9 +391,15 @@ int lbm_batch_run(lbm_batch_t *b, double tol, int check_every, long long max_ste
         bool changed = false;
         for (int i = 0; i < b->count; ++i) {
             if (!b->active[i]) continue;
+            // per-step relative change of the two probe densities over the check interval
+            const double dr = std::fmax(std::fabs(st[i].rho_probe_a - pa[i]) / st[i].rho_probe_a,
+                                        std::fabs(st[i].rho_probe_b - pb[i]) / st[i].rho_probe_b) /
+                              check_every;
+            pa[i] = st[i].rho_probe_a;
+            pb[i] = st[i].rho_probe_b;
             int status = 1;  // still running
             if (st[i].nonfinite) status = LBM_EUNSTABLE;
-            else if (st[i].dv_max / check_every < tol) status = LBM_OK;
+            else if (st[i].dv_max / check_every < tol && (!(tol_rho > 0) || dr < tol_rho)) status = LBM_OK;
             else if (b->steps[i] >= max_steps) status = LBM_ENOTCONVERGED;
             if (status != 1) {
                 b->active[i] = 0;

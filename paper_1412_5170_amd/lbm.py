@@ -54,6 +54,14 @@ class lbm_stats_t(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# torch (the source of device memory and streams) must bring up the GPU before this library's
+# HIP runtime does: a process where the library initialises HIP first cannot start torch's.
+try:
+    import torch as _torch
+    _torch.cuda.is_available()
+except ImportError:  # torch is optional for the C ABI itself
+    pass
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_5170_amd.build` "
                       "(there is no CPU fallback)")
@@ -246,7 +254,8 @@ _BSIG = {
     "lbm_batch_set_active": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_batch_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
-    "lbm_batch_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_longlong,
+    "lbm_batch_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_longlong,
                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]),
     "lbm_batch_read": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
     "lbm_batch_populations": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
@@ -320,11 +329,11 @@ class Batch:
             bcheck(rc, self.b)
         return [s.as_dict() for s in out]
 
-    def run(self, tol, check_every=100, max_steps=2_000_000):
+    def run(self, tol, check_every=100, max_steps=2_000_000, tol_rho=0.0):
         n = len(self.members)
         steps = (ctypes.c_longlong * n)()
         status = (ctypes.c_int * n)()
-        bcheck(lbm_batch_run(self.b, tol, check_every, max_steps, steps, status), self.b)
+        bcheck(lbm_batch_run(self.b, tol, tol_rho, check_every, max_steps, steps, status), self.b)
         return list(steps), list(status)
 
     def read(self, i):
@@ -343,3 +352,89 @@ class Batch:
 
     def steps(self, i):
         return int(lbm_batch_steps(self.b, i))
+
+
+# ---- learned warm start network ----------------------------------------------------------------
+_MSIG = {
+    "lbm_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P)]),
+    "lbm_mlp_destroy": (None, [_P]),
+    "lbm_mlp_param_count": (ctypes.c_size_t, [_P]),
+    "lbm_mlp_set_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_mlp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
+    "lbm_mlp_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P]),
+    "lbm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_float), _P]),
+    "lbm_mlp_last_error": (ctypes.c_char_p, [_P]),
+}
+for _name, (_res, _args) in _MSIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+class MLP:
+    """The library's GPU network; inputs and outputs are torch CUDA float32 tensors."""
+
+    def __init__(self, dims, seed=0):
+        self.dims = list(dims)
+        arr = (ctypes.c_int * len(dims))(*dims)
+        n = _P()
+        check(lbm_mlp_create(len(dims) - 1, arr, ctypes.byref(n)))
+        self.n = n
+        self.nparam = int(lbm_mlp_param_count(n))
+        # Glorot-uniform weights, zero biases (seeded).
+        rng = np.random.default_rng(seed)
+        parts = []
+        for i, o in zip(dims[:-1], dims[1:]):
+            lim = np.sqrt(6.0 / (i + o))
+            parts += [rng.uniform(-lim, lim, size=o * i), np.zeros(o)]
+        self.set_params(np.concatenate(parts).astype(np.float32))
+
+    def __del__(self):
+        n = getattr(self, "n", None)
+        if n:
+            lbm_mlp_destroy(n)
+            self.n = None
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LBMError(rc, lbm_mlp_last_error(self.n).decode())
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparam
+        self._check(lbm_mlp_set_params(self.n, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        p = np.empty(self.nparam, dtype=np.float32)
+        self._check(lbm_mlp_get_params(self.n, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    @staticmethod
+    def _stream():
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous().float()
+        y = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        self._check(lbm_mlp_forward(self.n, x.data_ptr(), x.shape[0], y.data_ptr(), self._stream()))
+        return y
+
+    def gradient(self, x, dy):
+        import torch
+        x = x.contiguous().float()
+        dy = dy.contiguous().float()
+        g = torch.empty(self.nparam, dtype=torch.float32, device=x.device)
+        self._check(lbm_mlp_gradient(self.n, x.data_ptr(), dy.data_ptr(), x.shape[0], g.data_ptr(),
+                                     self._stream()))
+        return g
+
+    def train_step(self, x, target, lr):
+        loss = ctypes.c_float()
+        self._check(lbm_mlp_train_step(self.n, x.data_ptr(), target.data_ptr(), x.shape[0],
+                                       float(lr), ctypes.byref(loss), self._stream()))
+        return loss.value

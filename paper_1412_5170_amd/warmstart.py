@@ -1,0 +1,229 @@
+"""Learned warm start for the batched droplet sweep.
+
+A small network (4 -> 128 -> 128 -> 128 -> 64, tanh, FP32, the library's own GPU forward,
+backward and Adam kernels) maps a droplet's (T/Tc, tau, R, K) to its equilibrium radial density
+profile (log rho at r_k = 2 R k / 63, k = 0..63).  It is trained on equilibria that the batched
+sweep itself produces from plain tanh initial states; at run time its profile initialises the
+lattice (f = f^eq(rho0, 0)), with the tanh profile as the fallback when a prediction is not a
+valid density.  Both runs stop on the same tolerances (velocity change and probe-density change
+per step); a much longer run from the tanh state gives the converged density ratio that the two are
+measured against.
+
+    python -m paper_1412_5170_amd.warmstart --out results.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, sweep
+
+DIMS = [4, 128, 128, 128, 64]
+K_RANGE = (1 / 49, 1 / 10)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def features(m):
+    """(T/Tc, tau, R, K) scaled to about [-1, 1] (R and K on a log scale)."""
+    return np.array([(m["T_over_Tc"] - 0.7) / 0.2,
+                     (m["tau"] - 1.05) / 0.45,
+                     (math.log(m["R"]) - math.log(48.0)) / math.log(2.0),
+                     (math.log(m["K"]) - 0.5 * math.log(K_RANGE[0] * K_RANGE[1]))
+                     / (0.5 * math.log(K_RANGE[1] / K_RANGE[0]))], dtype=np.float32)
+
+
+def draw_training(seed, count, n_min=96, n_step=16, n_levels=19):
+    """Training droplets drawn like the sweep, with K log-uniform in K_RANGE."""
+    draw = inputs.batch_draw(seed, count=count, n_min=n_min, n_step=n_step, n_levels=n_levels)
+    rng = np.random.default_rng(seed + 7919)
+    ms = sweep.members_from_draw(draw)
+    for m in ms:
+        m["K"] = float(math.exp(rng.uniform(math.log(K_RANGE[0]), math.log(K_RANGE[1]))))
+    return ms
+
+
+def equilibria(lbm, members, tol, check_every=500, max_steps=400_000, batch_size=64,
+               tol_rho=0.0):
+    """Run members to equilibrium from tanh states, in batches of similar size; returns the
+    radial log-density profiles, steps and statuses (in the members' order)."""
+    order = sorted(range(len(members)), key=lambda i: members[i]["nx"] * members[i]["ny"])
+    prof = np.full((len(members), sweep.PROFILE_POINTS), np.nan, dtype=np.float32)
+    steps = np.zeros(len(members), dtype=np.int64)
+    status = np.zeros(len(members), dtype=np.int64)
+    t0 = time.perf_counter()
+    for c in range(0, len(order), batch_size):
+        idx = order[c:c + batch_size]
+        ms = [members[i] for i in idx]
+        dens = [sweep.tanh_density(lbm, m) for m in ms]
+        wall, st, stat, b = sweep.run_batch(lbm, ms, dens, tol=tol, check_every=check_every,
+                                            max_steps=max_steps, tol_rho=tol_rho)
+        for j, i in enumerate(idx):
+            steps[i], status[i] = st[j], stat[j]
+            if stat[j] == 0:
+                rho, _ = b.read(j)
+                prof[i] = sweep.radial_profile(ms[j], rho)
+        del b
+        say(f"warmstart: equilibria {c + len(idx)}/{len(members)} (batch {wall:.1f} s, "
+            f"max steps {max(st)}, total {time.perf_counter() - t0:.1f} s)")
+    return prof, steps, status
+
+
+class Surrogate:
+    """The network plus the output standardisation learned from its training set."""
+
+    def __init__(self, lbm, seed=0):
+        self.lbm = lbm
+        self.net = lbm.MLP(DIMS, seed=seed)
+        self.mean = np.zeros(DIMS[-1], dtype=np.float32)
+        self.std = np.ones(DIMS[-1], dtype=np.float32)
+
+    def fit(self, X, Y, steps=6000, lr=1e-3, batch=256, seed=0, val_frac=0.1):
+        import torch
+        rng = np.random.default_rng(seed)
+        perm = rng.permutation(len(X))
+        nval = max(1, int(val_frac * len(X)))
+        val, tr = perm[:nval], perm[nval:]
+        self.mean = Y[tr].mean(axis=0).astype(np.float32)
+        self.std = (Y[tr].std(axis=0) + 1e-6).astype(np.float32)
+        Xt = torch.from_numpy(X[tr]).cuda()
+        Yt = torch.from_numpy(((Y[tr] - self.mean) / self.std).astype(np.float32)).cuda()
+        loss = None
+        for k in range(steps):
+            sel = torch.from_numpy(rng.integers(0, len(tr), size=min(batch, len(tr)))).cuda()
+            rate = lr * (0.5 * (1 + math.cos(math.pi * k / steps)) * 0.99 + 0.01)
+            loss = self.net.train_step(Xt[sel].contiguous(), Yt[sel].contiguous(), rate)
+            if k % 1000 == 0:
+                say(f"warmstart: train step {k}/{steps} loss {loss:.3e}")
+        pred = self.predict_log(X[val])
+        val_rmse = float(np.sqrt(np.mean((pred - Y[val]) ** 2)))
+        return {"train_loss_std_units": loss, "val_rmse_log_rho": val_rmse, "n_train": len(tr),
+                "n_val": int(nval)}
+
+    def predict_log(self, X):
+        import torch
+        y = self.net.forward(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda())
+        return y.cpu().numpy() * self.std + self.mean
+
+    def initial_density(self, m):
+        """Predicted initial density of member m, or None if it is not a valid density."""
+        prof = self.predict_log(features(m)[None])[0]
+        rho = sweep.profile_density(m, prof)
+        if not np.all(np.isfinite(rho)) or rho.min() <= 0 or rho.max() >= 0.99:  # 4/b = 1
+            return None
+        return rho
+
+
+def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho=0.0,
+             reference=True):
+    """Plain (tanh) and warm-started runs of the same members; wall time, steps and the
+    density ratio each reaches.  With `reference`, a third, untimed run from the tanh state for
+    a fixed 4x the plain run's longest step count (at least 100 000 steps) gives the converged
+    ratio that both are measured against."""
+    res = {}
+    modes = ("tanh", "learned") + (("reference",) if reference else ())
+    for mode in modes:
+        dens, fallback = [], 0
+        for m in members:
+            rho = sur.initial_density(m) if mode == "learned" else None
+            if rho is None:
+                rho = sweep.tanh_density(lbm, m)
+                fallback += mode == "learned"
+            dens.append(rho)
+        if mode == "reference":  # no convergence test: every member runs ref_steps
+            ref_steps = max(4 * max(res["tanh"]["steps"]), 100_000)
+            ref_steps += -ref_steps % check_every
+            run = dict(tol=1e-300, tol_rho=0.0, max_steps=ref_steps)
+        else:
+            run = dict(tol=tol, tol_rho=tol_rho, max_steps=max_steps)
+        wall, steps, status, b = sweep.run_batch(lbm, members, dens, check_every=check_every, **run)
+        ratios = []
+        for i, m in enumerate(members):
+            rho, _ = b.read(i)
+            ratios.append(float(rho[m["ny"] // 2, m["nx"] // 2] / rho[0, 0]))
+        del b
+        lu = sum(m["nx"] * m["ny"] * s for m, s in zip(members, steps))
+        res[mode] = {"wall_s": round(wall, 3), "steps": [int(s) for s in steps],
+                     "status": [int(s) for s in status], "ratio": ratios,
+                     "lattice_updates": int(lu), "fallbacks": fallback}
+        say(f"warmstart: {mode}: {wall:.2f} s, {lu / 1e9:.2f} G lattice updates, "
+            f"max steps {max(steps)}, not converged {sum(int(s != 0) for s in status)}")
+    rt, rl = np.array(res["tanh"]["ratio"]), np.array(res["learned"]["ratio"])
+    res["ratio_rel_diff_max"] = float(np.max(np.abs(rl - rt) / rt))
+    if reference:
+        rr = np.array(res["reference"]["ratio"])
+        res["ratio_err_tanh_max"] = float(np.max(np.abs(rt - rr) / rr))
+        res["ratio_err_learned_max"] = float(np.max(np.abs(rl - rr) / rr))
+        for i, m in enumerate(members):
+            say(f"warmstart: member {i} n={m['nx']} T/Tc={m['T_over_Tc']:.3f} tau={m['tau']:.3f} "
+                f"{m['collision']}: steps {res['tanh']['steps'][i]} -> "
+                f"{res['learned']['steps'][i]}, ratio {rt[i]:.6g} / {rl[i]:.6g} "
+                f"(reference {rr[i]:.6g})")
+    res["speedup_wall"] = res["tanh"]["wall_s"] / res["learned"]["wall_s"]
+    res["speedup_updates"] = res["tanh"]["lattice_updates"] / res["learned"]["lattice_updates"]
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-count", type=int, default=1024)
+    ap.add_argument("--train-tol", type=float, default=1e-8)
+    ap.add_argument("--train-levels", type=int, default=19, help="sizes 96 + 16 k, k < levels")
+    ap.add_argument("--eval-count", type=int, default=32)
+    ap.add_argument("--eval-levels", type=int, default=17, help="sizes 128 + 16 k, k < levels")
+    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--tol-rho", type=float, default=2e-9,
+                    help="per-step relative change of the probe densities at convergence")
+    ap.add_argument("--train-tol-rho", type=float, default=1e-8)
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--data", default=None, help="npz of (X, Y) to reuse instead of generating")
+    a = ap.parse_args(argv)
+    from . import lbm
+
+    out = {"dims": DIMS}
+    if a.data:
+        d = np.load(a.data)
+        X, Y = d["X"], d["Y"]
+    else:
+        tr = draw_training(1, a.train_count, n_levels=a.train_levels)
+        t0 = time.perf_counter()
+        prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
+        ok = status == 0
+        X = np.stack([features(m) for m in tr])[ok]
+        Y = prof[ok]
+        out["generation"] = {"members": len(tr), "converged": int(ok.sum()),
+                             "wall_s": round(time.perf_counter() - t0, 1), "tol": a.train_tol,
+                             "lattice_updates": int(sum(m["nx"] * m["ny"] * s
+                                                        for m, s in zip(tr, steps)))}
+        if a.out:
+            np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
+    sur = Surrogate(lbm, seed=0)
+    t0 = time.perf_counter()
+    out["training"] = sur.fit(X, Y, steps=a.train_steps)
+    out["training"]["wall_s"] = round(time.perf_counter() - t0, 1)
+    ev = sweep.members_from_draw(inputs.batch_draw(0, count=a.eval_count, n_levels=a.eval_levels))
+    out["evaluation"] = evaluate(lbm, sur, ev, a.tol, tol_rho=a.tol_rho)
+    out["evaluation"]["members"] = [{k: m[k] for k in ("nx", "T_over_Tc", "tau", "collision")}
+                                    for m in ev]
+    line = json.dumps(out)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(line + "\n")
+    say(json.dumps({k: out[k] for k in out if k != "evaluation"}))
+    e = out["evaluation"]
+    say(json.dumps({k: e[k] for k in ("speedup_wall", "speedup_updates", "ratio_rel_diff_max",
+                                      "ratio_err_tanh_max", "ratio_err_learned_max") if k in e}
+                   | {"tanh_wall_s": e["tanh"]["wall_s"],
+                      "learned_wall_s": e["learned"]["wall_s"]}))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

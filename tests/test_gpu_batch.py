@@ -72,7 +72,7 @@ def test_batch_run_drops_converged_and_unstable(L):
     b = L.Batch(members, tx=64)
     for i, m in enumerate(members):
         b.init(i, _rho0(m))
-    steps, status = b.run(tol=1e-7, check_every=100, max_steps=40000)
+    steps, status = b.run(tol=1e-7, check_every=100, max_steps=40000, tol_rho=1e-7)
     say(f"    steps {steps} status {status}")
     assert status[0] == 0 and status[1] == 0
     assert status[2] == L.LBM_EUNSTABLE
