@@ -194,6 +194,16 @@ int lbm_set_populations(lbm_t *h, const float *f);
  * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. Synchronises. */
 int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 
+/* Autotuner: times trial_steps steps of the one-pass sweep for strip widths tx in {64, 128,
+ * 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets XCD|SHALLOW, SHALLOW,
+ * XCD, XCD|SHALLOW|NONTEMPORAL (shapes are bitwise equivalent, so only speed differs), keeps the
+ * fastest and applies it with lbm_set_launch.  Runs on the current state, which it saves and
+ * restores (populations and step count), so the simulation resumes exactly where it was.
+ * cache_path (may be NULL): JSON lines keyed by device, size, scheme, collision, precision and
+ * layout; a hit applies the cached launch without trials (*ms_out = -1).  *ms_out (may be
+ * NULL): the best time per step in ms.  Needs lbm_init first.  Synchronises. */
+int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_out);
+
 /* Per-kernel timing with HIP events recorded on the handle's stream around every launch of
  * the two step kernels while enabled.  lbm_timing returns the summed milliseconds of the
  * density/psi pass and of the fused pass and the number of steps timed, then resets them. */
@@ -227,6 +237,36 @@ int lbm_batch_set_segment(lbm_batch_t *b, int i, int rows);
 /* f = f^eq(rho0, u0) for lattice i (host FP64 [ny][nx], u0 [ny][nx][2] or NULL); makes it
  * active and resets its step count. */
 int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0);
+
+/* Lattice i at physical rest with density rho0 (host FP64 [ny][nx]): f = f^eq(rho0, u) with
+ * u = -F / (2 rho0), F the interaction force of rho0 (Eq. 6 with psi of Eq. 7), so that the
+ * fluid velocity v = u + F / (2 rho) (Sec. 3) is zero everywhere.  A bare f^eq(rho0, 0) start
+ * (lbm_batch_init with u0 = NULL) gives every interface node the velocity F / (2 rho), an
+ * impulse whose ringing sets the time to equilibrium even from an exact equilibrium density.
+ * Makes the lattice active and resets its step count.  Synchronises. */
+int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0);
+
+/* Warm start of lattice i from a radial profile (the learned initial state): log_rho holds 64
+ * host values of log rho at r_k = 2 R k / 63, k = 0..63, r the distance from (nx/2, ny/2);
+ * rho(x, y) = exp(L(r / stretch)) with L the piecewise-linear interpolant (last value held beyond
+ * 2R), set at physical rest as in lbm_batch_init_rest.  mass > 0: the stretch in [1/4, 4] whose total
+ * density sum equals `mass` (relative 1e-13; bisection) -- in a periodic box the mass fixes the
+ * equilibrium, so a warm start must carry the mass of the state it replaces; mass <= 0: stretch
+ * 1.  *stretch_out (may be NULL) receives the stretch.  LBM_EINVAL if a value is not finite or
+ * no stretch reaches the mass; LBM_EUNSTABLE if the density leaves (0, 4/b).  Makes the lattice
+ * active and resets its step count.  Synchronises. */
+int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double R, double mass,
+                           double *stretch_out);
+
+/* Autotuner for the batch: times trial_steps (even) steps of every lattice for strip widths
+ * tx in {64, 128, 256} with and without LBM_LAUNCH_SHALLOW, then, per size class (lattices whose
+ * longer side rounds up to the same power of two), segment heights {8, 16, 32, 64}; keeps the
+ * fastest and applies it.  Needs every lattice initialised; saves and restores the populations,
+ * step counts and activity flags, so the batch resumes exactly where it was.  cache_path (may be
+ * NULL): JSON lines keyed by device and the multiset of (size, scheme, collision); a hit
+ * applies the cached choice without trials (*ms_out = -1).  *ms_out (may be NULL): the best
+ * time per step in ms.  Synchronises. */
+int lbm_batch_autotune(lbm_batch_t *b, const char *cache_path, int trial_steps, double *ms_out);
 
 /* Include (1) or exclude (0) an initialised lattice from stepping. */
 int lbm_batch_set_active(lbm_batch_t *b, int i, int active);

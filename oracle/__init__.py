@@ -11,6 +11,7 @@ HIP library or its Python binding.
 * ``bruteforce``    -- the literal equations with explicit tensor sums on tiny lattices,
                        used to pin the C stepper.
 * ``mlp``           -- FP64 reference of the warm-start network's forward/backward pass.
+* ``profile``       -- the warm-start initial state: radial profile to lattice, mass matching.
 """
 from __future__ import annotations
 

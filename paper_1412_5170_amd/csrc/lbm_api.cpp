@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -495,6 +496,94 @@ int lbm_step(lbm_t *h, int n) {
         h->cur = 1 - h->cur;
         ++h->step;
     }
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_out) {
+    if (!h || trial_steps < 1) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_autotune before lbm_init");
+    std::ostringstream key;
+    key << pplbm::device_tag() << "|single|" << h->p.nx << "x" << h->p.ny << "|scheme" << h->p.scheme
+        << "|coll" << h->p.coll << "|prec" << h->prec << "|layout" << h->layout;
+    std::string hit;
+    if (pplbm::tune_cache_lookup(cache_path, key.str(), &hit)) {
+        int k = 0, tx = 0, ty = 0, fl = 0;
+        if (std::sscanf(hit.c_str(), "%d %d %d %d", &k, &tx, &ty, &fl) == 4 &&
+            lbm_set_launch(h, k, tx, ty, fl) == LBM_OK) {
+            if (ms_out) *ms_out = -1.0;  // from the cache, not timed now
+            return LBM_OK;
+        }
+    }
+    // Trials run on the current state; it is saved first and restored afterwards.
+    const size_t fbytes = 9 * h->p.plane * sizeof(float);
+    float *saved = nullptr;
+    if (hipMalloc(&saved, fbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, LBM_ENOMEM, "autotune: state copy allocation failed");
+    }
+    const int cur0 = h->cur;
+    const long long step0 = h->step;
+    const bool timing0 = h->timing;  // steps leave vprev alone, so its snapshot stays valid
+    const pplbm::Launch before = h->launch;
+    h->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = LBM_OK;
+    hipError_t he = hipMemcpyAsync(saved, h->f[cur0], fbytes, hipMemcpyDeviceToDevice, h->stream);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    pplbm::Launch best = before;
+    double best_ms = 1e300;
+    const int txs[] = {64, 128, 256, 512};
+    const int tys[] = {4, 8, 16, 32, 64};
+    const int fls[] = {pplbm::kFlagXCD | pplbm::kFlagShallow, pplbm::kFlagShallow,
+                       pplbm::kFlagXCD, pplbm::kFlagXCD | pplbm::kFlagShallow | pplbm::kFlagNT};
+    const int width = (int)std::min<size_t>(h->p.pitch, 512);
+    for (int tx : txs) {
+        if (he != hipSuccess || rc) break;
+        if (tx > 64 && tx > width) continue;  // strips wider than the lattice only idle
+        for (int ty : tys) {
+            if (ty > 8 && ty / 2 >= h->p.ny) continue;
+            for (int fl : fls) {
+                if (he != hipSuccess || rc) break;
+                rc = lbm_set_launch(h, LBM_KERNEL_SWEEP, tx, ty, fl);
+                if (!rc) rc = lbm_step(h, 2);  // warm-up (first-launch costs)
+                if (rc) break;
+                he = hipEventRecord(e0, h->stream);
+                if (he == hipSuccess) rc = lbm_step(h, trial_steps);
+                if (he == hipSuccess && !rc) he = hipEventRecord(e1, h->stream);
+                if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
+                float ms = 0;
+                if (he == hipSuccess && !rc) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he == hipSuccess && !rc && ms / trial_steps < best_ms) {
+                    best_ms = ms / trial_steps;
+                    best = h->launch;
+                }
+            }
+        }
+    }
+    // restore the state whatever happened
+    hipError_t he2 = hipMemcpyAsync(h->f[cur0], saved, fbytes, hipMemcpyDeviceToDevice, h->stream);
+    if (he2 == hipSuccess) he2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(saved);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    h->cur = cur0;
+    h->step = step0;
+    h->timing = timing0;
+    if (he != hipSuccess) {
+        h->launch = before;
+        return hip_fail(h, he, "autotune trial");
+    }
+    if (he2 != hipSuccess) return hip_fail(h, he2, "autotune restore");
+    if (rc) {
+        h->launch = before;
+        return rc;
+    }
+    h->launch = best;
+    std::ostringstream val;
+    val << best.kernel << " " << best.tx << " " << best.ty << " " << best.flags;
+    pplbm::tune_cache_store(cache_path, key.str(), val.str(), best_ms);
+    if (ms_out) *ms_out = best_ms;
     return LBM_OK;
 }
 

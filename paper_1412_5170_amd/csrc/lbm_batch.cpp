@@ -9,8 +9,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -290,6 +292,254 @@ int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0) 
     b->steps[i] = 0;
     b->vprev_valid[i] = 0;
     return upload_tiles(b);
+}
+
+namespace {
+// f0 of lattice i, holding f^eq(rho, 0), becomes the force-consistent rest state.
+int rest_state(lbm_batch *b, int i) {
+    const Physics &p = b->phys[i];
+    float *psi = nullptr;
+    if (hipMalloc(&psi, p.plane * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, LBM_ENOMEM, "psi scratch allocation failed");
+    }
+    hipError_t e = pplbm::launch_rest(p, b->f0[i], psi, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(psi);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("rest state: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0) {
+    int rc = lbm_batch_init(b, i, rho0, nullptr);
+    if (rc) return rc;
+    rc = rest_state(b, i);
+    if (rc) b->initialised[i] = b->active[i] = 0;
+    return rc ? rc : upload_tiles(b);
+}
+
+int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double R, double mass,
+                           double *stretch_out) {
+    if (!b || i < 0 || i >= b->count || !log_rho || !(R > 0))
+        return bfail(b, LBM_EINVAL, "lbm_batch_init_profile: bad argument");
+    for (int k = 0; k < 64; ++k)
+        if (!std::isfinite(log_rho[k])) return bfail(b, LBM_EINVAL, "non-finite profile value");
+    const Physics &p = b->phys[i];
+    const int nb = pplbm::profile_mass_blocks(p);
+    double *part = nullptr;
+    if (hipMalloc(&part, 3 * (size_t)nb * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, LBM_ENOMEM, "staging allocation failed");
+    }
+    std::vector<double> host(3 * (size_t)nb);
+    double lo_rho = 0, hi_rho = 0;
+    // total mass, min and max density of the profile at a stretch (partials added in order)
+    auto measure = [&](double stretch, double *sum) -> hipError_t {
+        hipError_t e = pplbm::launch_profile_mass(p, log_rho, R, stretch, part, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return e;
+        double s = 0, lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < nb; ++k) {
+            s += host[3 * k];
+            lo = std::fmin(lo, host[3 * k + 1]);
+            hi = std::fmax(hi, host[3 * k + 2]);
+        }
+        *sum = s;
+        lo_rho = lo;
+        hi_rho = hi;
+        return hipSuccess;
+    };
+    double stretch = 1.0, m = 0;
+    hipError_t e = hipSuccess;
+    int rc = LBM_OK;
+    if (mass > 0) {
+        // the total mass is monotone in the stretch for a profile denser inside than outside
+        // (a droplet) or the reverse (a bubble); bisection on [1/4, 4]
+        double lo = 0.25, hi = 4.0, f_lo = 0, f_hi = 0;
+        e = measure(lo, &f_lo);
+        if (e == hipSuccess) e = measure(hi, &f_hi);
+        f_lo -= mass;
+        f_hi -= mass;
+        if (e == hipSuccess && !((f_lo < 0 && f_hi > 0) || (f_lo > 0 && f_hi < 0))) {
+            rc = bfail(b, LBM_EINVAL, "no stretch of the profile in [1/4, 4] carries that mass");
+        } else {
+            for (int it = 0; e == hipSuccess && it < 200; ++it) {
+                stretch = 0.5 * (lo + hi);
+                e = measure(stretch, &m);
+                if (e != hipSuccess) break;
+                const double d = m - mass;
+                if (std::fabs(d) <= 1e-13 * mass) break;
+                if ((d < 0) == (f_lo < 0)) {
+                    lo = stretch;
+                    f_lo = d;
+                } else {
+                    hi = stretch;
+                }
+            }
+        }
+    }
+    if (e == hipSuccess && rc == LBM_OK) e = measure(stretch, &m);
+    if (e == hipSuccess && rc == LBM_OK && !(lo_rho > 0 && p.b_quarter * hi_rho < 1))
+        rc = bfail(b, LBM_EUNSTABLE, "profile density outside (0, 4/b)");
+    if (e == hipSuccess && rc == LBM_OK) e = pplbm::launch_profile_init(p, log_rho, R, stretch, b->f0[i], b->stream);
+    if (e == hipSuccess && rc == LBM_OK) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(part);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("lbm_batch_init_profile: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    rc = rest_state(b, i);
+    if (rc) return rc;
+    if (stretch_out) *stretch_out = stretch;
+    b->initialised[i] = 1;
+    b->active[i] = 1;
+    b->steps[i] = 0;
+    b->vprev_valid[i] = 0;
+    return upload_tiles(b);
+}
+
+namespace {
+int size_class(const Physics &p) {  // ceil(log2(longer side))
+    int c = 0;
+    while ((1 << c) < std::max(p.nx, p.ny)) ++c;
+    return c;
+}
+}  // namespace
+
+int lbm_batch_autotune(lbm_batch_t *b, const char *cache_path, int trial_steps, double *ms_out) {
+    if (!b || trial_steps < 2 || trial_steps % 2) return bfail(b, LBM_EINVAL, "trial_steps: even, >= 2");
+    for (int i = 0; i < b->count; ++i)
+        if (!b->initialised[i]) return bfail(b, LBM_ESTATE, "lbm_batch_autotune before every lattice is initialised");
+    // key: device and the multiset of (size, scheme, collision)
+    std::vector<std::string> sig;
+    for (int i = 0; i < b->count; ++i) {
+        const Physics &p = b->phys[i];
+        sig.push_back(std::to_string(p.nx) + "x" + std::to_string(p.ny) + "s" + std::to_string(p.scheme) + "c" +
+                      std::to_string(p.coll));
+    }
+    std::sort(sig.begin(), sig.end());
+    unsigned long long hsh = 1469598103934665603ull;  // FNV-1a
+    for (const std::string &t : sig)
+        for (char c : t + ";") hsh = (hsh ^ (unsigned char)c) * 1099511628211ull;
+    std::vector<int> classes;
+    for (int i = 0; i < b->count; ++i) classes.push_back(size_class(b->phys[i]));
+    std::vector<int> distinct = classes;
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    char hex[24];
+    std::snprintf(hex, sizeof hex, "%016llx", hsh);
+    const std::string key = pplbm::device_tag() + "|batch|" + std::to_string(b->count) + "|" + hex;
+
+    auto apply = [&](int tx, int fl, const std::vector<int> &rows_of_class) -> int {
+        for (int i = 0; i < b->count; ++i) {
+            const size_t c = std::lower_bound(distinct.begin(), distinct.end(), classes[i]) - distinct.begin();
+            b->seg_rows[i] = rows_of_class[c];
+        }
+        return lbm_batch_set_launch(b, tx, b->groups, fl);
+    };
+    std::string hit;
+    if (pplbm::tune_cache_lookup(cache_path, key, &hit)) {
+        std::istringstream in(hit);
+        int tx = 0, fl = 0;
+        std::vector<int> rows(distinct.size(), 32);
+        bool ok = static_cast<bool>(in >> tx >> fl);
+        for (size_t c = 0; ok && c < distinct.size(); ++c) ok = static_cast<bool>(in >> rows[c]) && rows[c] >= 1;
+        if (ok && apply(tx, fl, rows) == LBM_OK) {
+            if (ms_out) *ms_out = -1.0;
+            return LBM_OK;
+        }
+    }
+    // save the current populations (every lattice sits at an even step, so in f0)
+    std::vector<float *> saved(b->count, nullptr);
+    int rc = LBM_OK;
+    for (int i = 0; i < b->count && !rc; ++i) {
+        const size_t fb = 9 * b->phys[i].plane * sizeof(float);
+        if (hipMalloc(&saved[i], fb) != hipSuccess) {
+            (void)hipGetLastError();
+            saved[i] = nullptr;
+            rc = bfail(b, LBM_ENOMEM, "autotune: state copy allocation failed");
+        } else if (hipMemcpyAsync(saved[i], b->f0[i], fb, hipMemcpyDeviceToDevice, b->stream) != hipSuccess) {
+            rc = bfail(b, LBM_EHIP, "autotune: state copy failed");
+        }
+    }
+    const std::vector<long long> steps0 = b->steps;
+    const std::vector<char> active0 = b->active;
+    const int tx0 = b->tx, fl0 = b->flags;
+    std::vector<int> rows0(distinct.size(), 32);
+    for (int i = 0; i < b->count; ++i)
+        rows0[std::lower_bound(distinct.begin(), distinct.end(), classes[i]) - distinct.begin()] = b->seg_rows[i];
+    for (int i = 0; i < b->count; ++i) b->active[i] = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = bfail(b, LBM_EHIP, "autotune: event creation failed");
+    auto trial = [&](int tx, int fl, const std::vector<int> &rows, double *ms) -> int {
+        int r = apply(tx, fl, rows);
+        if (!r) r = lbm_batch_step(b, 2);
+        if (r) return r;
+        BHIP(b, hipEventRecord(e0, b->stream));
+        r = lbm_batch_step(b, trial_steps);
+        if (r) return r;
+        BHIP(b, hipEventRecord(e1, b->stream));
+        BHIP(b, hipEventSynchronize(e1));
+        float t = 0;
+        BHIP(b, hipEventElapsedTime(&t, e0, e1));
+        *ms = t / trial_steps;
+        return LBM_OK;
+    };
+    int best_tx = tx0, best_fl = fl0;
+    std::vector<int> best_rows = rows0;
+    double best_ms = 1e300, ms = 0;
+    // stage 1: strip width and prefetch depth at the current segment heights
+    for (int tx : {64, 128, 256}) {
+        for (int fl : {pplbm::kFlagShallow, 0}) {
+            if (rc) break;
+            rc = trial(tx, fl, rows0, &ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                best_tx = tx;
+                best_fl = fl;
+            }
+        }
+    }
+    // stage 2: segment height per size class, one class at a time
+    for (size_t c = 0; c < distinct.size() && !rc; ++c) {
+        for (int rows : {8, 16, 32, 64}) {
+            if (rc) break;
+            std::vector<int> cand = best_rows;
+            cand[c] = rows;
+            rc = trial(best_tx, best_fl, cand, &ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                best_rows = cand;
+            }
+        }
+    }
+    // restore the state and the activity flags whatever happened
+    for (int i = 0; i < b->count; ++i) {
+        if (saved[i]) {
+            if (hipMemcpyAsync(b->f0[i], saved[i], 9 * b->phys[i].plane * sizeof(float), hipMemcpyDeviceToDevice,
+                               b->stream) != hipSuccess && !rc)
+                rc = bfail(b, LBM_EHIP, "autotune: state restore failed");
+        }
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = bfail(b, LBM_EHIP, "autotune: sync failed");
+    for (float *q : saved)
+        if (q) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->steps = steps0;
+    b->active = active0;
+    const int rc2 = rc ? apply(tx0, fl0, rows0) : apply(best_tx, best_fl, best_rows);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    std::ostringstream val;
+    val << best_tx << " " << best_fl;
+    for (int r : best_rows) val << " " << r;
+    pplbm::tune_cache_store(cache_path, key, val.str(), best_ms);
+    if (ms_out) *ms_out = best_ms;
+    return LBM_OK;
 }
 
 int lbm_batch_step(lbm_batch_t *b, int n) {

@@ -604,6 +604,73 @@ __global__ void __launch_bounds__(256) init_kernel(Physics p, const double *__re
     }
 }
 
+// Radial-profile initial state (warm start): rho(x, y) = exp(L(r / stretch)), r the distance
+// from the lattice centre (nx/2, ny/2), L the piecewise-linear interpolant of the 64 values
+// log rho at r_k = 2 R k / 63 (the last value held beyond 2R); f = f^eq(rho, 0).
+constexpr int kProfilePoints = 64;
+
+struct Profile {
+    double v[kProfilePoints];  // log rho at r_k
+    double dr;                 // r_1 - r_0 = 2R / 63
+    double inv_stretch;
+};
+
+__device__ __forceinline__ double profile_rho(const Profile &P, int nx, int ny, int x, int y) {
+    const double dx = x - 0.5 * nx, dy = y - 0.5 * ny;
+    const double t = sqrt(dx * dx + dy * dy) * P.inv_stretch / P.dr;
+    int k = (int)t;
+    double l;
+    if (k >= kProfilePoints - 1) {
+        l = P.v[kProfilePoints - 1];
+    } else {
+        const double w = t - k;
+        l = P.v[k] + w * (P.v[k + 1] - P.v[k]);
+    }
+    return exp(l);
+}
+
+__global__ void __launch_bounds__(256) profile_init_kernel(Physics p, Profile P,
+                                                           float *__restrict__ f) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= p.nx) return;
+    for (int y = blockIdx.y; y < p.ny; y += gridDim.y) {
+        const double rho = profile_rho(P, p.nx, p.ny, x, y);
+        const size_t i = (size_t)y * p.frow + x;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[i + q * p.fq] = (float)(wgt<double>(q) * rho);
+    }
+}
+
+// Sum, min and max of the profile density over the lattice: one partial triple per block in a
+// fixed pattern; the host adds the partials in block order.
+__global__ void __launch_bounds__(256) profile_mass_kernel(int nx, int ny, Profile P,
+                                                           double *__restrict__ partial) {
+    __shared__ double sh[3][256];
+    double s = 0.0, lo = INFINITY, hi = -INFINITY;
+    const size_t N = (size_t)nx * ny;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (size_t)gridDim.x * 256) {
+        const int y = (int)(k / nx), x = (int)(k - (size_t)y * nx);
+        const double r = profile_rho(P, nx, ny, x, y);
+        s += r;
+        lo = fmin(lo, r);
+        hi = fmax(hi, r);
+    }
+    const int t = threadIdx.x;
+    sh[0][t] = s;
+    sh[1][t] = lo;
+    sh[2][t] = hi;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sh[0][t] += sh[0][t + h];
+            sh[1][t] = fmin(sh[1][t], sh[1][t + h]);
+            sh[2][t] = fmax(sh[2][t], sh[2][t + h]);
+        }
+        __syncthreads();
+    }
+    if (t < 3) partial[3 * (size_t)blockIdx.x + t] = sh[t][0];
+}
+
 struct NodeMacro {
     double rho, vx, vy;
     bool finite;
@@ -636,6 +703,24 @@ __device__ __forceinline__ NodeMacro node_macro(const Physics &p, const float *_
     m.vy = jy / rho + Fy / (2.0 * rho);
     m.finite = isfinite(rho) && isfinite(m.vx) && isfinite(m.vy) && isfinite(pc);
     return m;
+}
+
+// Rest state consistent with the force: f holds f^eq(rho, 0) and psi the plane of that state;
+// each node is rewritten in place as f^eq(rho, u) with u = -F / (2 rho), so that the physical
+// velocity v = u + F / (2 rho) (Sec. 3) starts at zero.  A bare f^eq(rho, 0) start carries
+// v = F / (2 rho) at every interface, an impulse that rings for thousands of steps.
+__global__ void __launch_bounds__(256) rest_kernel(Physics p, float *__restrict__ f,
+                                                   const float *__restrict__ psi) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= p.nx) return;
+    for (int y = blockIdx.y; y < p.ny; y += gridDim.y) {
+        const NodeMacro m = node_macro(p, f, psi, x, y);  // j = 0, so v = F / (2 rho)
+        double s[9];
+        eq_shape<double>(-m.vx, -m.vy, s);
+        const size_t i = (size_t)y * p.frow + x;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[i + q * p.fq] = (float)(wgt<double>(q) * m.rho * (1.0 + s[q]));
+    }
 }
 
 __global__ void __launch_bounds__(256) macro_kernel(Physics p, const float *__restrict__ f,
@@ -923,10 +1008,46 @@ hipError_t launch_init(const Physics &p, const double *rho0, const double *u0, f
     return hipGetLastError();
 }
 
+hipError_t launch_rest(const Physics &p, float *f, float *psi, hipStream_t s) {
+    hipError_t e = launch_psi(p, kPrecF64, 0, f, psi, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rest_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, p, f, psi);
+    return hipGetLastError();
+}
+
 hipError_t launch_macro(const Physics &p, const float *f, const float *psi, double *rho,
                         double *u, hipStream_t s) {
     hipLaunchKernelGGL(macro_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, p, f, psi, rho,
                        u);
+    return hipGetLastError();
+}
+
+namespace {
+Profile make_profile(const double *log_rho, double R, double stretch) {
+    Profile P;
+    for (int k = 0; k < kProfilePoints; ++k) P.v[k] = log_rho[k];
+    P.dr = 2.0 * R / (kProfilePoints - 1);
+    P.inv_stretch = 1.0 / stretch;
+    return P;
+}
+}  // namespace
+
+int profile_mass_blocks(const Physics &p) {
+    const size_t N = (size_t)p.nx * p.ny, b = (N + 255) / 256;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_profile_mass(const Physics &p, const double *log_rho, double R, double stretch,
+                               double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(profile_mass_kernel, dim3(profile_mass_blocks(p)), dim3(256), 0, s, p.nx,
+                       p.ny, make_profile(log_rho, R, stretch), partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_init(const Physics &p, const double *log_rho, double R, double stretch,
+                               float *f, hipStream_t s) {
+    hipLaunchKernelGGL(profile_init_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, p,
+                       make_profile(log_rho, R, stretch), f);
     return hipGetLastError();
 }
 

@@ -224,6 +224,14 @@ class Lattice:
     def set_launch(self, kernel, tx, ty, flags=0):
         check(lbm_set_launch(self.h, kernel, tx, ty, flags), self.h)
 
+    def autotune(self, cache_path=None, trial_steps=20):
+        """Pick the fastest sweep launch by timed trials on the current state (restored
+        afterwards) and apply it; returns ms per step of the winner (-1: cache hit)."""
+        ms = ctypes.c_double(0.0)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        check(lbm_autotune(self.h, path, int(trial_steps), ctypes.byref(ms)), self.h)
+        return ms.value
+
     def get_launch(self):
         v = [ctypes.c_int() for _ in range(4)]
         check(lbm_get_launch(self.h, *(ctypes.byref(x) for x in v)), self.h)
@@ -251,6 +259,11 @@ _BSIG = {
     "lbm_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_set_segment": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_init": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+    "lbm_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int, _D]),
+    "lbm_batch_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int, _D]),
+    "lbm_batch_init_rest": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "lbm_batch_init_profile": (ctypes.c_int, [_P, ctypes.c_int, _D, ctypes.c_double,
+                                              ctypes.c_double, _D]),
     "lbm_batch_set_active": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_batch_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
@@ -312,6 +325,31 @@ class Batch:
         assert rho0.shape == (m["ny"], m["nx"])
         u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
         bcheck(lbm_batch_init(self.b, i, _dptr(rho0), _dptr(u0)), self.b)
+
+    def init_rest(self, i, rho0):
+        """f = f^eq(rho0, -F/(2 rho0)): the density at physical rest (v = 0)."""
+        m = self.members[i]
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert rho0.shape == (m["ny"], m["nx"])
+        bcheck(lbm_batch_init_rest(self.b, i, _dptr(rho0)), self.b)
+
+    def init_profile(self, i, log_rho, R, mass=0.0):
+        """Warm start from 64 values of log rho at r_k = 2 R k / 63; with mass > 0 the profile
+        is stretched radially to carry exactly that total mass.  Returns the stretch."""
+        log_rho = np.ascontiguousarray(log_rho, dtype=np.float64)
+        assert log_rho.shape == (64,)
+        stretch = ctypes.c_double(0.0)
+        bcheck(lbm_batch_init_profile(self.b, i, _dptr(log_rho), float(R), float(mass),
+                                      ctypes.byref(stretch)), self.b)
+        return stretch.value
+
+    def autotune(self, cache_path=None, trial_steps=20):
+        """Pick strip width, prefetch depth and segment heights per size class by timed trials
+        (state restored afterwards); returns ms per step of the winner (-1: cache hit)."""
+        ms = ctypes.c_double(0.0)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        bcheck(lbm_batch_autotune(self.b, path, int(trial_steps), ctypes.byref(ms)), self.b)
+        return ms.value
 
     def set_active(self, i, on):
         bcheck(lbm_batch_set_active(self.b, i, int(on)), self.b)

@@ -1,6 +1,6 @@
 """Batched parameter sweeps of static droplets (the sweeps over tau and T/Tc of Sec. 4, as one
 job on one GPU): members drawn by `inputs.batch_draw`, initialised from a tanh profile or from
-a predicted radial profile, advanced by the library's batched sweep until the per-step change
+a predicted radial profile (expanded on the device), advanced by the library's batched sweep until the per-step change
 of the velocity field falls below a tolerance.
 
 Physics of every member (the droplet workloads): Guo forcing with Li's term, sigma = 0.125
@@ -45,15 +45,6 @@ def profile_radii(R):
     return 2.0 * R * np.arange(PROFILE_POINTS) / (PROFILE_POINTS - 1)
 
 
-def profile_density(m, log_profile):
-    """2-D initial density from a radial profile of log rho at r_k: linear in r, the last value
-    held beyond 2R (distance from the lattice centre, as the tanh initialiser)."""
-    nx, ny, R = m["nx"], m["ny"], m["R"]
-    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
-    r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2)
-    return np.exp(np.interp(r, profile_radii(R), np.asarray(log_profile, dtype=np.float64)))
-
-
 def radial_profile(m, rho):
     """log rho of a field sampled at the 64 profile radii along the +x axis from the centre
     (linear interpolation between nodes)."""
@@ -65,14 +56,33 @@ def radial_profile(m, rho):
     return np.log(np.interp(xs, np.arange(nx), line))
 
 
-def run_batch(lbm, members, densities, tol=1e-9, check_every=100, max_steps=400_000, tx=128,
+class WarmStart:
+    """A predicted radial profile (64 values of log rho at the profile radii), stretched on the
+    device to carry `mass`; `fallback` (a density array) is used if the library rejects it."""
+
+    def __init__(self, log_profile, mass, fallback):
+        self.log_profile = np.asarray(log_profile, dtype=np.float64)
+        self.mass = float(mass)
+        self.fallback = fallback
+
+
+def run_batch(lbm, members, inits, tol=1e-9, check_every=100, max_steps=400_000, tx=128,
               segment=None, tol_rho=0.0):
     """Advance all members to equilibrium (velocity change per step < tol and, if tol_rho > 0,
-    relative change per step of the probe densities < tol_rho); returns wall seconds, steps,
-    statuses, batch."""
+    relative change per step of the probe densities < tol_rho).  inits[i] is a density array
+    or a WarmStart; either starts at physical rest (v = 0).  Returns wall seconds, steps, statuses and the batch (its `fallbacks`
+    counts warm starts that fell back)."""
     b = lbm.Batch(members, tx=tx)
-    for i, rho0 in enumerate(densities):
-        b.init(i, rho0)
+    b.fallbacks = 0
+    for i, init in enumerate(inits):
+        if isinstance(init, WarmStart):
+            try:
+                b.init_profile(i, init.log_profile, members[i]["R"], init.mass)
+            except lbm.LBMError:
+                b.fallbacks += 1
+                b.init_rest(i, init.fallback)
+        else:
+            b.init_rest(i, init)
         if segment is not None:
             b.set_segment(i, segment(members[i]))
     b.sync()

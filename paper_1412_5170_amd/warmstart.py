@@ -3,9 +3,10 @@
 A small network (4 -> 128 -> 128 -> 128 -> 64, tanh, FP32, the library's own GPU forward,
 backward and Adam kernels) maps a droplet's (T/Tc, tau, R, K) to its equilibrium radial density
 profile (log rho at r_k = 2 R k / 63, k = 0..63).  It is trained on equilibria that the batched
-sweep itself produces from plain tanh initial states; at run time its profile initialises the
-lattice (f = f^eq(rho0, 0)), with the tanh profile as the fallback when a prediction is not a
-valid density.  Both runs stop on the same tolerances (velocity change and probe-density change
+sweep itself produces from plain tanh initial states; at run time its profile, expanded on the device
+and stretched radially so that its total mass equals that of the tanh state it replaces (in a
+periodic box the mass fixes the equilibrium), initialises the lattice (f = f^eq(rho0, 0)), with
+the tanh state as the fallback when a prediction is not a valid density.  Both runs stop on the same tolerances (velocity change and probe-density change
 per step); a much longer run from the tanh state gives the converged density ratio that the two are
 measured against.
 
@@ -112,13 +113,15 @@ class Surrogate:
         y = self.net.forward(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda())
         return y.cpu().numpy() * self.std + self.mean
 
-    def initial_density(self, m):
-        """Predicted initial density of member m, or None if it is not a valid density."""
+    def warm_start(self, lbm, m):
+        """The learned initial state of member m: its predicted profile, to be stretched on the
+        device to the mass of the tanh state it replaces (in a periodic box the mass fixes the
+        equilibrium), with that tanh state as the fallback."""
+        plain = sweep.tanh_density(lbm, m)
         prof = self.predict_log(features(m)[None])[0]
-        rho = sweep.profile_density(m, prof)
-        if not np.all(np.isfinite(rho)) or rho.min() <= 0 or rho.max() >= 0.99:  # 4/b = 1
-            return None
-        return rho
+        if not np.all(np.isfinite(prof)):
+            return plain
+        return sweep.WarmStart(prof, plain.sum(), plain)
 
 
 def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho=0.0,
@@ -130,20 +133,20 @@ def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho
     res = {}
     modes = ("tanh", "learned") + (("reference",) if reference else ())
     for mode in modes:
-        dens, fallback = [], 0
-        for m in members:
-            rho = sur.initial_density(m) if mode == "learned" else None
-            if rho is None:
-                rho = sweep.tanh_density(lbm, m)
-                fallback += mode == "learned"
-            dens.append(rho)
+        if mode == "learned":
+            inits = [sur.warm_start(lbm, m) for m in members]
+        else:
+            inits = [sweep.tanh_density(lbm, m) for m in members]
+        fallback = sum(not isinstance(x, sweep.WarmStart) for x in inits) if mode == "learned" else 0
         if mode == "reference":  # no convergence test: every member runs ref_steps
             ref_steps = max(4 * max(res["tanh"]["steps"]), 100_000)
             ref_steps += -ref_steps % check_every
             run = dict(tol=1e-300, tol_rho=0.0, max_steps=ref_steps)
         else:
             run = dict(tol=tol, tol_rho=tol_rho, max_steps=max_steps)
-        wall, steps, status, b = sweep.run_batch(lbm, members, dens, check_every=check_every, **run)
+        wall, steps, status, b = sweep.run_batch(lbm, members, inits, check_every=check_every,
+                                                 **run)
+        fallback += b.fallbacks
         ratios = []
         for i, m in enumerate(members):
             rho, _ = b.read(i)

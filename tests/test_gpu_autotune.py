@@ -1,0 +1,88 @@
+"""Autotuner: trials leave the simulation exactly where it was, the chosen launch is one of
+the candidates, the JSON-lines cache is written and reused, and a tuned run is bitwise equal
+to an untuned one (every launch shape computes the same bits)."""
+import json
+
+import numpy as np
+import pytest
+
+from lbm_cases import say
+from oracle import thermo as TH
+from paper_1412_5170_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1412_5170_amd import lbm
+    return lbm
+
+
+def _lattice(L, nx, ny):
+    lat = L.Lattice(nx, ny, L.make_eos(0.6, K=1 / 49), L.make_force("GUO_LI", sigma=0.125),
+                    L.make_collision("MRT"), 0.9)
+    g, l, _ = TH.maxwell(0.6)
+    lat.init(inputs.droplet(nx, ny, min(nx, ny) / 4, 5.0, l, g))
+    return lat
+
+
+def test_single_autotune_restores_state_and_caches(L, tmp_path):
+    say("autotune single 256x130")
+    cache = tmp_path / "tune.jsonl"
+    a, b = _lattice(L, 256, 130), _lattice(L, 256, 130)
+    a.step(10)
+    b.step(10)
+    before = a.populations()
+    ms = a.autotune(str(cache), trial_steps=4)
+    assert ms > 0
+    assert np.array_equal(a.populations(), before)
+    assert a.stats()["step"] == 10
+    k, tx, ty, fl = a.get_launch()
+    assert k == L.LBM_KERNEL_SWEEP and tx in (64, 128, 256, 512) and ty in (4, 8, 16, 32, 64)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert "256x130" in rec["key"] and rec["value"] == f"{k} {tx} {ty} {fl}"
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.populations(), b.populations())
+    # a second handle of the same problem takes the cached choice without trials
+    c = _lattice(L, 256, 130)
+    assert c.autotune(str(cache), trial_steps=4) == -1.0
+    assert c.get_launch() == (k, tx, ty, fl)
+    assert len(cache.read_text().splitlines()) == 1
+
+
+def test_batch_autotune_restores_state(L, tmp_path):
+    say("autotune batch")
+    members = [dict(nx=n, ny=n, T_over_Tc=0.7, K=1 / 49, scheme="GUO_LI", sigma=0.125,
+                    collision=c, tau=1.0) for n, c in ((96, "BGK"), (160, "MRT"), (200, "BGK"))]
+
+    def make():
+        bt = L.Batch(members)
+        for i, m in enumerate(members):
+            g, l, _ = TH.maxwell(m["T_over_Tc"])
+            bt.init(i, inputs.droplet(m["nx"], m["ny"], m["nx"] / 4, 5.0, l, g))
+        return bt
+
+    a, b = make(), make()
+    a.step(10)
+    b.step(10)
+    a.set_active(1, 0)
+    b.set_active(1, 0)
+    before = [a.populations(i) for i in range(3)]
+    cache = tmp_path / "batch.jsonl"
+    ms = a.autotune(str(cache), trial_steps=4)
+    assert ms > 0
+    for i in range(3):
+        assert np.array_equal(a.populations(i), before[i])
+    assert [a.steps(i) for i in range(3)] == [10, 10, 10]
+    a.step(10)
+    b.step(10)
+    assert [a.steps(i) for i in range(3)] == [20, 10, 20]  # lattice 1 stayed inactive
+    for i in range(3):
+        assert np.array_equal(a.populations(i), b.populations(i))
+    assert make().autotune(str(cache), trial_steps=4) == -1.0

@@ -1,0 +1,125 @@
+"""Warm-start initial states on the device (lbm_batch_init_rest, lbm_batch_init_profile)
+against the oracle of the rest state, the profile expansion and the mass matching; error
+paths; and the gain itself: a lattice started at rest from its own equilibrium density needs
+far fewer steps than the tanh start and reaches the same density ratio, and so, to a lesser
+degree, does the mass-matched radial profile of that equilibrium."""
+import oracle
+from oracle import thermo as TH
+import numpy as np
+import pytest
+
+from lbm_cases import say
+from oracle import profile as oprof
+from paper_1412_5170_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1412_5170_amd import lbm
+    return lbm
+
+
+def _member(nx, ny, **kw):
+    m = dict(nx=nx, ny=ny, T_over_Tc=0.7, K=1 / 49, scheme="GUO_LI", sigma=0.125,
+             collision="BGK", tau=1.0)
+    m.update(kw)
+    return m
+
+
+def _oracle_params(m):
+    return oracle.Params(nx=m["nx"], ny=m["ny"], T=m["T_over_Tc"] * TH.critical_point()[1],
+                         K=m["K"], scheme=oracle.GUO_LI, sigma=m["sigma"], tau=m["tau"])
+
+
+def _profile(R, inner=0.35, outer=0.02, width=4.0):
+    r = oprof.radii(R)
+    return np.log(outer + (inner - outer) * 0.5 * (1 - np.tanh((r - R) / width)))
+
+
+@pytest.mark.parametrize("nx,ny,R,stretch", [(130, 96, 20.0, 1.0), (64, 200, 12.5, 1.37),
+                                             (5, 3, 1.0, 1.0)])
+def test_profile_init_matches_oracle(L, nx, ny, R, stretch):
+    say(f"profile init {nx}x{ny} R={R} stretch={stretch}")
+    m = _member(nx, ny)
+    prof = _profile(R)
+    b = L.Batch([m])
+    mass = oprof.density(nx, ny, R, prof, stretch).sum() if stretch != 1.0 else 0.0
+    s = b.init_profile(0, prof, R, mass)
+    if stretch == 1.0:
+        assert s == 1.0
+    else:
+        assert abs(s - stretch) < 1e-9
+    f = b.populations(0).astype(np.float64)
+    rho_ref = oprof.density(nx, ny, R, prof, s)
+    ref = oprof.rest_populations(_oracle_params(m), rho_ref)
+    # FP32 storage, and a force from the FP32-rounded rest populations
+    assert np.max(np.abs(f - ref) / ref) < 1e-6
+    rho, v = b.read(0)
+    assert np.max(np.abs(rho - rho_ref) / rho_ref) < 1e-6
+    assert np.max(np.abs(v)) < 1e-6
+    st = b.stats()[0]
+    if mass:
+        assert abs(st["mass"] - mass) / mass < 1e-6
+    assert b.steps(0) == 0
+
+
+def test_profile_init_errors(L):
+    b = L.Batch([_member(64, 64)])
+    flat = np.log(np.full(64, 0.1))
+    with pytest.raises(L.LBMError) as e:
+        b.init_profile(0, flat, 16.0, 2 * 0.1 * 64 * 64)  # no stretch changes a uniform mass
+    assert e.value.code == L.LBM_EINVAL
+    bad = _profile(16.0)
+    bad[5] = np.nan
+    with pytest.raises(L.LBMError) as e:
+        b.init_profile(0, bad, 16.0)
+    assert e.value.code == L.LBM_EINVAL
+    dense = np.log(np.full(64, 1.2))  # above the packing limit 4/b = 1
+    with pytest.raises(L.LBMError) as e:
+        b.init_profile(0, dense, 16.0)
+    assert e.value.code == L.LBM_EUNSTABLE
+    assert b.stats()[0]["step"] == 0  # a rejected profile leaves the lattice uninitialised
+
+def test_rest_state_matches_oracle(L):
+    m = _member(96, 80)
+    g, l, _ = TH.maxwell(0.7)
+    rho0 = inputs.droplet(96, 80, 20.0, 5.0, l, g)
+    b = L.Batch([m])
+    b.init_rest(0, rho0)
+    f = b.populations(0).astype(np.float64)
+    ref = oprof.rest_populations(_oracle_params(m), rho0)
+    assert np.max(np.abs(f - ref) / ref) < 1e-6
+    rho, v = b.read(0)
+    assert np.max(np.abs(v)) < 1e-6
+
+
+def test_warm_start_gain(L):
+    """From the droplet's own equilibrium density at physical rest: at most half the steps of
+    the tanh start, same density ratio.  From the mass-matched radial profile of that
+    equilibrium (64 samples along +x): fewer steps, same ratio."""
+    from paper_1412_5170_amd import sweep
+    m = dict(sweep.PHYSICS, nx=128, ny=128, T_over_Tc=0.7, tau=1.0, collision="BGK", R=32.0)
+    plain = sweep.tanh_density(L, m)
+    run = dict(tol=1e-9, tol_rho=2e-9, check_every=500, max_steps=200_000)
+    w0, s0, st0, b0 = sweep.run_batch(L, [m], [plain], **run)
+    assert st0 == [0]
+    rho0, _ = b0.read(0)
+    ratio0 = rho0[64, 64] / rho0[0, 0]
+    w1, s1, st1, b1 = sweep.run_batch(L, [m], [rho0], **run)
+    rho1, _ = b1.read(0)
+    ratio1 = rho1[64, 64] / rho1[0, 0]
+    prof = sweep.radial_profile(m, rho0)
+    w2, s2, st2, b2 = sweep.run_batch(L, [m], [sweep.WarmStart(prof, plain.sum(), plain)], **run)
+    rho2, _ = b2.read(0)
+    ratio2 = rho2[64, 64] / rho2[0, 0]
+    say(f"warm start gain: steps tanh {s0[0]}, exact rest {s1[0]}, profile {s2[0]}; "
+        f"ratio {ratio0:.8g} / {ratio1:.8g} / {ratio2:.8g}")
+    assert st1 == [0] and st2 == [0] and b2.fallbacks == 0
+    assert s1[0] <= s0[0] // 2
+    assert s2[0] < s0[0]
+    assert abs(ratio1 - ratio0) / ratio0 < 1e-4
+    assert abs(ratio2 - ratio0) / ratio0 < 1e-4

@@ -1,0 +1,120 @@
+"""Host-side logic of the batched sweep and the warm start (no GPU), and the oracle of the
+warm-start initial state (radial profile to lattice, mass matching) pinned to geometry."""
+import math
+
+import numpy as np
+
+from oracle import profile as oprof
+from paper_1412_5170_amd import inputs, sweep, warmstart
+
+
+def _member(n=160, R=40.0):
+    return dict(sweep.PHYSICS, nx=n, ny=n, R=R, T_over_Tc=0.6, tau=1.0, collision="BGK")
+
+
+def test_profile_radii_agree():
+    assert np.array_equal(sweep.profile_radii(37.5), oprof.radii(37.5))
+    assert sweep.PROFILE_POINTS == oprof.POINTS == 64
+
+
+def test_profile_round_trip():
+    """A smooth radial profile expanded to the lattice and sampled back along +x is itself."""
+    m = _member()
+    r = sweep.profile_radii(m["R"])
+    prof = np.log(0.2 + 0.19 * np.tanh((30.0 - r) / 6.0))
+    rho = oprof.density(m["nx"], m["ny"], m["R"], prof)
+    back = sweep.radial_profile(m, rho)
+    # two linear interpolations (profile to lattice, lattice to profile) of a steep log profile
+    assert np.max(np.abs(back - prof)) < 2e-2
+    assert np.median(np.abs(back - prof)) < 1e-3
+
+
+def test_profile_is_rest_equilibrium():
+    prof = np.log(np.linspace(0.3, 0.01, 64))
+    f = oprof.populations(40, 30, 10.0, prof)
+    rho = oprof.density(40, 30, 10.0, prof)
+    assert np.allclose(f.sum(axis=0), rho, rtol=1e-15)
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    assert np.abs(np.tensordot(ex, f, 1)).max() < 1e-17
+    assert np.abs(np.tensordot(ey, f, 1)).max() < 1e-17
+
+
+def test_profile_centre_and_far_field():
+    """The centre node takes the first value, nodes beyond 2R s take the last."""
+    prof = np.log(np.linspace(0.4, 0.02, 64))
+    rho = oprof.density(64, 64, 8.0, prof, stretch=1.5)
+    assert math.isclose(rho[32, 32], 0.4, rel_tol=1e-15)
+    assert math.isclose(rho[0, 0], 0.02, rel_tol=1e-15)  # r = 45 > 2 R s = 24
+
+
+def test_mass_match_disk_closed_form():
+    """A sharp disk (rho_l inside radius a, rho_g outside) holds about
+    rho_g N + (rho_l - rho_g) pi (a s)^2: the matched stretch follows that area law."""
+    n, R = 256, 40.0
+    r = oprof.radii(R)
+    a = 30.0
+    rl, rg = 0.4, 0.01
+    # a steep but resolved edge between profile radii (the profile is linear between them)
+    prof = np.log(np.where(r < a, rl, rg))
+    for s_true in (0.8, 1.0, 1.3):
+        area = math.pi * (a * s_true) ** 2
+        mass = rg * n * n + (rl - rg) * area
+        s = oprof.mass_matched_stretch(n, n, R, prof, mass)
+        assert s is not None
+        assert abs(s - s_true) / s_true < 0.02  # lattice count of a disk vs its area
+
+
+def test_mass_match_is_exact_and_monotone():
+    m = _member()
+    r = sweep.profile_radii(m["R"])
+    prof = np.log(0.2 + 0.19 * np.tanh((35.0 - r) / 4.0))
+    base = oprof.density(m["nx"], m["ny"], m["R"], prof).sum()
+    for target in (0.9 * base, base, 1.2 * base):
+        s = oprof.mass_matched_stretch(m["nx"], m["ny"], m["R"], prof, target)
+        assert s is not None
+        assert abs(oprof.density(m["nx"], m["ny"], m["R"], prof, s).sum() - target) <= 1e-12 * target
+    # stretching a droplet (dense inside) raises its mass
+    d = lambda s: oprof.density(m["nx"], m["ny"], m["R"], prof, s).sum()
+    assert d(1.1) > base > d(0.9)
+
+
+def test_mass_match_unreachable_is_none():
+    prof = np.log(np.full(64, 0.1))  # uniform: no stretch changes the mass
+    assert oprof.mass_matched_stretch(160, 160, 40.0, prof, 2.0 * 0.1 * 160 * 160) is None
+
+
+def test_features_span_unit_box():
+    ms = warmstart.draw_training(3, 256)
+    X = np.stack([warmstart.features(m) for m in ms])
+    assert X.shape == (256, 4) and X.dtype == np.float32
+    assert np.all(np.abs(X) <= 1.0 + 1e-6)
+    assert all(warmstart.K_RANGE[0] <= m["K"] <= warmstart.K_RANGE[1] for m in ms)
+
+
+def test_batch_draw_seeded_and_in_range():
+    a = inputs.batch_draw(5, count=64)
+    b = inputs.batch_draw(5, count=64)
+    assert a == b
+    for d in a:
+        assert 128 <= d.n <= 128 + 16 * 56 and (d.n - 128) % 16 == 0
+        assert 0.5 <= d.T_over_Tc <= 0.9 and 0.6 <= d.tau <= 1.5
+        assert math.isclose(d.R, d.n / 4) or d.R <= d.n / 2
+
+
+def test_rest_populations_have_zero_fluid_velocity():
+    """The rest state keeps the density and makes v = u + F/(2 rho) vanish, while F itself is
+    far from zero across the interface (a sign slip would leave v = -F / rho)."""
+    import oracle
+    from oracle import thermo as TH
+    nx = ny = 48
+    g, l, _ = TH.maxwell(0.7)
+    rho = inputs.droplet(nx, ny, 12.0, 5.0, l, g)
+    p = oracle.Params(nx=nx, ny=ny, T=0.7 * TH.critical_point()[1], K=1 / 49,
+                      scheme=oracle.GUO_LI, sigma=0.125, tau=1.0)
+    f = oprof.rest_populations(p, rho)
+    fl = oracle.fields(p, f)
+    assert np.allclose(fl["rho"], rho, rtol=1e-14, atol=0)
+    F = np.hypot(fl["Fx"], fl["Fy"]) / (2 * rho)
+    assert F.max() > 1e-4
+    assert np.abs(fl["vx"]).max() < 1e-15 and np.abs(fl["vy"]).max() < 1e-15
