@@ -8,7 +8,10 @@ A step is one full time step -- by default the one-pass sweep kernel (psi recomp
 populations, force, forcing, collision and streaming in one launch); --kernel two_pass runs the
 density/psi pass and the fused pass instead -- and the FP64 observables reduction runs every
 --stats-every steps inside the timed region, as a production run would.  Inputs are resident in
-HBM before timing starts.
+HBM before timing starts.  The sweep runs the library's default launch
+(256-column strips, 8-row segments, two rows of loads in flight, XCD-ordered tiles: the
+fastest shape measured on this workload); --autotune lets the library's autotuner pick
+(timed trials on the initial state, which it restores, before the warm-up), --launch sets it.
 
 Prints ONE JSON line: MLUPS, the HBM roofline of the dominant kernel measured with HIP events
 on the lattice's stream (algorithmic bytes per launch / average launch time), the same for the
@@ -44,6 +47,8 @@ def parse():
     ap.add_argument("--workload", default="droplet_4096_mrt")
     ap.add_argument("--precision", default="mixed", choices=["f32", "f64", "mixed"])
     ap.add_argument("--kernel", default="sweep", choices=["sweep", "two_pass"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the sweep's launch with the library's autotuner first")
     ap.add_argument("--launch", default=None,
                     help="tx,ty[,flags] of the kernel (default: the library's choice)")
     ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
@@ -191,8 +196,13 @@ def main():
     timing = not args.no_timing
 
     lat = make_lattice(lbm, wl, args, args.kernel)
-    launch = lat.get_launch()
     lat.init(rho0)
+    tuned_ms = None
+    if args.kernel == "sweep" and not args.launch and args.autotune:
+        # the library's autotuner (timed trials on this state, restored afterwards), before
+        # the warm-up and outside the timed region
+        tuned_ms = lat.autotune(None, trial_steps=50)
+    launch = lat.get_launch()
     print(f"bench: {args.workload} {wl['nx']}x{wl['ny']} {args.precision} {args.kernel} "
           f"launch {launch}, warmup {args.warmup}", file=sys.stderr, flush=True)
     lat.step(args.warmup)
@@ -237,7 +247,8 @@ def main():
         "config": {"workload": args.workload, "nx": wl["nx"], "ny": wl["ny"],
                    "collision": wl["collision"], "scheme": wl["scheme"],
                    "T_over_Tc": wl["T_over_Tc"], "K": wl["K"], "tau": wl["tau"],
-                   "kernel": args.kernel, "launch": list(launch), "layout": args.layout,
+                   "kernel": args.kernel, "launch": list(launch),
+                   "autotuned": tuned_ms is not None, "layout": args.layout,
                    "stats_every": args.stats_every, "parallelism": "single GPU"},
         "roofline": roofline(args.kernel, ev) if ev else None,
     }

@@ -155,7 +155,9 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *   LBM_KERNEL_SWEEP: one kernel per step; a workgroup of tx threads (multiple of 64, <= 512)
  *     sweeps a strip of tx columns over segments of ty rows, computing psi from the
  *     populations as it loads them, so each population is read once: 72 bytes per node and
- *     step plus the strip and segment edges.
+ *     step plus the strip and segment edges.  Addresses the populations through 32-bit
+ *     buffer offsets, so 9 * 4 * pitch * ny must stay below 4 GiB (LBM_EINVAL otherwise; such
+ *     lattices default to the two-pass step).  The batch's lattices obey the same limit.
  * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
  *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
  *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */

@@ -160,19 +160,20 @@ int maxwell(const lbm_eos &e, double *rho_g, double *rho_l) {
     return LBM_OK;
 }
 
-// One-pass sweep with strips as wide as 256 columns and segments as tall as 32 rows, narrowed
-// and shortened (down to 64 x 8) until the launch has about 1024 workgroups to spread over the
-// 256 compute units.  lbm_set_launch or an autotuned choice replaces it.
+// One-pass sweep with strips as wide as 256 columns and segments as tall as 8 rows, two rows
+// of loads in flight and XCD-ordered tiles (the fastest measured shape on the 4096^2 MRT
+// droplet), narrowed and shortened (down to 64 x 4) until the launch has about 1024
+// workgroups to spread over the 256 compute units.  lbm_set_launch or lbm_autotune replaces it.
 pplbm::Launch default_launch(int nx, int ny) {
     pplbm::Launch L;
     L.kernel = pplbm::kKernelSweep;
-    L.flags = pplbm::kFlagXCD | pplbm::kFlagShallow;
+    L.flags = pplbm::kFlagXCD;
     L.tx = 256;
-    L.ty = 32;
+    L.ty = 8;
     auto groups = [&]() { return (double)((nx + L.tx - 1) / L.tx) * ((ny + L.ty - 1) / L.ty); };
-    while (groups() < 1024 && (L.tx > 64 || L.ty > 8)) {
+    while (groups() < 1024 && (L.tx > 64 || L.ty > 4)) {
         if (L.tx > 64 && (L.tx >= 2 * 64 && nx <= L.tx * 4)) L.tx /= 2;
-        else if (L.ty > 8) L.ty /= 2;
+        else if (L.ty > 4) L.ty /= 2;
         else L.tx /= 2;
     }
     return L;
@@ -313,6 +314,11 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     h->xa = nx / 2;
     h->ya = ny / 2;
     h->launch = default_launch(nx, ny);
+    if (pplbm::pop_bytes(p) > pplbm::kSweepMaxBytes) {  // beyond 32-bit buffer offsets
+        h->launch.kernel = pplbm::kKernelTwoPass;
+        h->launch.tx = 256;
+        h->launch.ty = 4;
+    }
     *out = h;
     return LBM_OK;
 }
@@ -401,6 +407,8 @@ int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags) {
     } else if (kernel == LBM_KERNEL_SWEEP) {
         if (tx < 64 || tx % 64 || tx > 512 || ty < 1)
             return fail(h, LBM_EINVAL, "sweep: tx a multiple of 64 up to 512, ty >= 1 rows");
+        if (pplbm::pop_bytes(h->p) > pplbm::kSweepMaxBytes)
+            return fail(h, LBM_EINVAL, "sweep: population buffer beyond 4 GiB (use the two-pass step)");
     } else {
         return fail(h, LBM_EINVAL, "unknown kernel");
     }

@@ -176,6 +176,7 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
         std::string why;
         int rc = pplbm::make_physics(nx[i], ny[i], &eos[i], &force[i], &coll[i], tau[i], &b->phys[i],
                                      nullptr, &why);
+        if (!rc && pplbm::pop_bytes(b->phys[i]) > pplbm::kSweepMaxBytes) rc = LBM_EINVAL;
         if (rc) {
             delete b;
             return rc;

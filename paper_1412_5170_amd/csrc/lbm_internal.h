@@ -110,6 +110,11 @@ hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblock
                               const int2 *ranges, const int *ids, int nlat, int parity, int track,
                               double *partial, double *out, hipStream_t stream);
 
+// Bytes of one population buffer (9 velocity planes).  The one-pass sweep addresses it
+// through 32-bit buffer offsets, so it needs this below 4 GiB.
+inline size_t pop_bytes(const Physics &p) { return 9 * p.plane * sizeof(float); }
+constexpr size_t kSweepMaxBytes = 0xFFFFFFFFull;
+
 // Autotuner cache (JSON lines; see lbm_tune.cpp).
 std::string device_tag();
 bool tune_cache_lookup(const char *path, const std::string &key, std::string *value);

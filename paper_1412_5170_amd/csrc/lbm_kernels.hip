@@ -58,15 +58,30 @@ __device__ __forceinline__ T density9(const float f[9]) {
 
 // Effective density of Eq. 7 with the rescaled Carnahan-Starling pressure of Eq. 29-30.
 // NaN when the node is outside the EOS (b rho/4 >= 1) or 2 U / G <= 0.
+// 1 / x for x > 0 from the hardware reciprocal refined by Newton steps (two in FP64, none in
+// FP32): within an ulp or two of the correctly rounded quotient at a fraction of its cost.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_amdgcn_rcpf(x);
+    } else {
+        T r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, T(1)), r);
+        return fma(r, fma(-x, r, T(1)), r);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T eos_psi(T rho, T bq, T RT, T a, T K, T two_over_G) {
     const T eta = bq * rho;
     if (!(eta < T(1)) || !(rho > T(0))) return qnan<T>();
     const T om = T(1) - eta;
-    const T Z = (T(1) + eta * (T(1) + eta * (T(1) - eta))) / (om * om * om);
+    const T Z = (T(1) + eta * (T(1) + eta * (T(1) - eta))) * recip<T>(om * om * om);
     const T p0 = K * (rho * (RT * Z - a * rho));
-    const T r = two_over_G * (p0 - rho / T(3));
-    return r > T(0) ? sqrt(r) : qnan<T>();
+    const T r = two_over_G * (p0 - rho * (T(1) / T(3)));
+    // psi is stored in FP32, so its square root is the hardware FP32 one (1 ulp) of the
+    // radicand rounded once.
+    return r > T(0) ? T(__builtin_amdgcn_sqrtf((float)r)) : qnan<T>();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -77,6 +92,7 @@ struct StepConst {
     int nx, ny;
     size_t pitch;      // psi row stride (floats)
     size_t frow, fq;   // population row and velocity strides (floats)
+    unsigned fbytes;   // bytes of one population buffer (the one-pass sweep needs < 4 GiB)
     int flags;         // kFlagNT | kFlagXCD
     D bq, RT, a, K, two_over_G;  // EOS (Eq. 29-30) and Eq. 7
     D gA;     // -G A / 2        coefficient of sum w psi^2 e    (Eq. 6, U = G psi^2 / 2)
@@ -130,6 +146,16 @@ __device__ __forceinline__ void eq_minus_f(D rho_d, R ux, R uy, const float f[9]
     }
 }
 
+// 1 / psi^2 for Li's term (Eq. 31): a small correction, so FP32 takes the hardware
+// reciprocal (1 ulp) instead of a correctly rounded division.
+template <typename R>
+__device__ __forceinline__ R inv_sq(float pc) {
+    if constexpr (sizeof(R) == 4)
+        return __builtin_amdgcn_rcpf(pc * pc);
+    else
+        return R(1) / (R(pc) * R(pc));
+}
+
 // Guo's bracket B_q = w_q [3 e.F + 9 (e.F)(e.V) - 3 F.V] (Eq. 23 with c_s^2 = 1/3).
 template <typename R>
 __device__ __forceinline__ void guo_bracket(R Fx, R Fy, R Vx, R Vy, R B[9]) {
@@ -170,10 +196,11 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
     const D rho_d = density9<D>(f);
     const D jx = (((D)f[1] - (D)f[3]) + ((D)f[5] - (D)f[7])) + ((D)f[8] - (D)f[6]);
     const D jy = (((D)f[2] - (D)f[4]) + ((D)f[5] - (D)f[7])) + ((D)f[6] - (D)f[8]);
-    const D uxd = jx / rho_d, uyd = jy / rho_d;
+    const D inv = recip<D>(rho_d), hinv = D(0.5) * inv;
+    const D uxd = jx * inv, uyd = jy * inv;
     const R rho = (R)rho_d;
     const R ux = (R)uxd, uy = (R)uyd;
-    const R vx = (R)(uxd + Fxd / (D(2) * rho_d)), vy = (R)(uyd + Fyd / (D(2) * rho_d));
+    const R vx = (R)(uxd + Fxd * hinv), vy = (R)(uyd + Fyd * hinv);
     const R Fx = (R)Fxd, Fy = (R)Fyd;
     const R pc = p.c;
 
@@ -184,7 +211,7 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
             // Eq. 22 with f^eq(rho, u + D) - f^eq(rho, u) written out exactly:
             // w rho [3 e.D + 9/2 (e.D)(e.(2u + D)) - 3/2 D.(2u + D)],  D = F / rho.
             eq_minus_f<R, D>(rho_d, ux, uy, f, neq);
-            const R Dx = Fx / rho, Dy = Fy / rho;
+            const R Dx = (R)(Fxd * inv), Dy = (R)(Fyd * inv);
             const R Sx = R(2) * ux + Dx, Sy = R(2) * uy + Dy;
             const R DS = R(1.5) * (Dx * Sx + Dy * Sy);
             const R eD[9] = {R(0), Dx, Dy, -Dx, -Dy, Dx + Dy, Dy - Dx, -Dx - Dy, Dx - Dy};
@@ -199,7 +226,7 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
             eq_minus_f<R, D>(rho_d, vx, vy, f, neq);
             R bx = vx, by = vy;
             if constexpr (SCHEME == GUO_LI) {
-                const R cl = c.li / (pc * pc);
+                const R cl = c.li * inv_sq<R>(pc);
                 bx = vx + cl * Fx;
                 by = vy + cl * Fy;
             }
@@ -232,7 +259,7 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         R S[9] = {R(0), R(6) * vF, -R(6) * vF, Fx, -Fx, Fy, -Fy,
                   R(2) * (vx * Fx - vy * Fy), vx * Fy + vy * Fx};
         if constexpr (SCHEME == GUO_LI) {
-            const R cl = c.li2 / (pc * pc);
+            const R cl = c.li2 * inv_sq<R>(pc);
             const R Xxx = cl * Fx * Fx, Xyy = cl * Fy * Fy, Xxy = cl * Fx * Fy;
             const R tr3 = R(3) * (Xxx + Xyy);
             S[1] += tr3 * c.lim[1];
@@ -296,6 +323,59 @@ __device__ __forceinline__ void stream_out(float *__restrict__ fout, const StepC
 __device__ __forceinline__ void load9(const float *__restrict__ f, size_t i, size_t fq, float v[9]) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) v[q] = f[i + q * fq];
+}
+
+// Buffer-resource access for the one-pass sweep: the population buffer is one 128-bit
+// resource in scalar registers; a node's address is a 32-bit per-lane byte offset (its column)
+// plus a wave-uniform scalar offset (row and velocity plane), so the nine loads and nine
+// stores of a node share three per-lane offsets (x, x + 1, x - 1) instead of eighteen 64-bit
+// pointers.  The resource also bounds every access by the buffer size.
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit access on CDNA
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const float *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+
+__device__ __forceinline__ void bload9(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                       unsigned qstride, float v[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        v[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff + q * qstride, 0));
+}
+
+__device__ __forceinline__ void bput(__amdgpu_buffer_rsrc_t r, float v, unsigned voff,
+                                     unsigned soff, bool nt) {
+    if (nt)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 2);  // nt
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Push streaming (Eq. 36) through the buffer resource.
+template <typename R, typename D>
+__device__ __forceinline__ void bstream_out(__amdgpu_buffer_rsrc_t r, const StepConst<R, D> &c,
+                                            int x, int y, const float fs[9], bool nt) {
+    const unsigned vx = 4u * x, ve = 4u * (x + 1 == c.nx ? 0 : x + 1),
+                   vw = 4u * (x == 0 ? c.nx - 1 : x - 1);
+    const int yn = y + 1 == c.ny ? 0 : y + 1, ys = y == 0 ? c.ny - 1 : y - 1;
+    const unsigned q = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
+    const unsigned rc = fr * y, rn = fr * yn, rs = fr * ys;
+    auto all = [&](auto put1) {
+        put1(fs[0], vx, rc);
+        put1(fs[1], ve, q + rc);
+        put1(fs[2], vx, 2 * q + rn);
+        put1(fs[3], vw, 3 * q + rc);
+        put1(fs[4], vx, 4 * q + rs);
+        put1(fs[5], ve, 5 * q + rn);
+        put1(fs[6], vw, 6 * q + rn);
+        put1(fs[7], vw, 7 * q + rs);
+        put1(fs[8], ve, 8 * q + rs);
+    };
+    if (nt)
+        all([&](float v, unsigned vo, unsigned so) { bput(r, v, vo, so, true); });
+    else
+        all([&](float v, unsigned vo, unsigned so) { bput(r, v, vo, so, false); });
 }
 
 // Block index remapped so that consecutive tiles land on the same XCD (workgroups are dealt
@@ -394,10 +474,11 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
 
 // ---------------------------------------------------------------------------------------
 // One-pass step: a workgroup of TX threads owns a strip of TX columns and sweeps a segment of
-// H rows upwards.  psi is computed from the populations as each row is loaded and kept in a
+// H rows (upwards or downwards).  psi is computed from the populations as each row is loaded and kept in a
 // four-row LDS ring (plus the two halo columns, computed by lanes 0 and 1), so every
 // population is read from memory once per step; only the halo columns and the row below and
-// above the segment are read twice.  Rows are software-pipelined two deep: while row y is
+// above the segment are read twice (neighbouring segments sweep in opposite directions, so
+// that second read comes from L2).  Rows are software-pipelined two deep: while row y is
 // collided, row y+1 (loaded one iteration earlier) becomes psi and the loads of row y+2 are
 // in flight.  Same per-node arithmetic as the two-pass step, bit for bit.
 // ---------------------------------------------------------------------------------------
@@ -415,10 +496,12 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     const bool halo = tx < 2;                    // lanes 0 and 1 also own the halo columns
     const int x = x0 + tx;
     const int y1 = y0 + H < ny ? y0 + H : ny;
-    const size_t fq = c.fq, frow = c.frow;
     const int hcol = tx == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + na == nx ? 0 : x0 + na);
     const int hslot = tx == 0 ? 0 : na + 1;
     const bool nt = c.flags & kFlagNT;
+    const __amdgpu_buffer_rsrc_t rin = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
+    const unsigned qs = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
+    const unsigned vx = 4u * x, vh = 4u * hcol;
     auto wrapy = [&](int yy) { return yy >= ny ? yy - ny : (yy < 0 ? yy + ny : yy); };
     auto slot = [&](int yy_rel) { return ring + ((yy_rel + 1) & 3) * W; };
 
@@ -427,56 +510,65 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     // bottom, straight into the ring slot of row y+2 (that slot held row y-2, which no thread
     // reads in iteration y; iteration y+1 reads it after its barrier).
     // PF = 1: row y+1 is loaded and turned into psi at the top of iteration y.
+    // Segments alternate direction (even ones sweep up, odd ones down), so the two segments
+    // that share a boundary read the boundary rows at the same time -- both at their start or
+    // both at their end -- and the second read of those rows hits in L2.  Row k of the sweep
+    // is ys + dir k; the ring keeps rows k-1 ("behind"), k and k+1 ("ahead").
+    const int nrow = y1 - y0;
+    const int dir = ((y0 / H) & 1) ? -1 : 1;
+    const int ys = dir > 0 ? y0 : y1 - 1;
+    auto row = [&](int k) { return wrapy(ys + dir * k); };
     float fa[9], fb[9], fc[9], hc[9];
     {
-        const int ym = wrapy(y0 - 1), yp = wrapy(y0 + 1);
-        if (active) load9(fin, (size_t)ym * frow + x, fq, fc);
-        if (active) load9(fin, (size_t)y0 * frow + x, fq, fa);
+        const unsigned rm = fr * row(-1), r0 = fr * row(0), rp = fr * row(1);
+        if (active) bload9(rin, vx, rm, qs, fc);
+        if (active) bload9(rin, vx, r0, qs, fa);
         if (active) slot(-1)[tx + 1] = c.psi_of(fc);
         if (active) slot(0)[tx + 1] = c.psi_of(fa);
-        if (PF == 2 && active) load9(fin, (size_t)yp * frow + x, fq, fb);
+        if (PF == 2 && active) bload9(rin, vx, rp, qs, fb);
         if (halo) {
-            load9(fin, (size_t)ym * frow + hcol, fq, hc);
+            bload9(rin, vh, rm, qs, hc);
             slot(-1)[hslot] = c.psi_of(hc);
-            load9(fin, (size_t)y0 * frow + hcol, fq, hc);
+            bload9(rin, vh, r0, qs, hc);
             slot(0)[hslot] = c.psi_of(hc);
             if (PF == 2) {
-                load9(fin, (size_t)yp * frow + hcol, fq, hc);
+                bload9(rin, vh, rp, qs, hc);
                 slot(1)[hslot] = c.psi_of(hc);
             }
         }
     }
-    for (int y = y0; y < y1; ++y) {
-        float *rn = slot(y - y0 + 1);
+    for (int k = 0; k < nrow; ++k) {
+        float *ahead = slot(k + 1);
         bool more = false;
         if constexpr (PF == 2) {
-            // Row y+2 is needed only while row y+1 is still inside the segment.
-            more = y + 2 <= y1;
+            // Row k+2 is needed only while row k+1 is still inside the segment.
+            more = k + 2 <= nrow;
             if (more) {
-                const size_t r2 = (size_t)wrapy(y + 2) * frow;
-                if (active) load9(fin, r2 + x, fq, fc);
-                if (halo) load9(fin, r2 + hcol, fq, hc);
+                const unsigned r2 = fr * row(k + 2);
+                if (active) bload9(rin, vx, r2, qs, fc);
+                if (halo) bload9(rin, vh, r2, qs, hc);
             }
         } else {
-            const size_t r1 = (size_t)wrapy(y + 1) * frow;
-            if (active) load9(fin, r1 + x, fq, fb);
+            const unsigned r1 = fr * row(k + 1);
+            if (active) bload9(rin, vx, r1, qs, fb);
             if (halo) {
-                load9(fin, r1 + hcol, fq, hc);
-                rn[hslot] = c.psi_of(hc);
+                bload9(rin, vh, r1, qs, hc);
+                ahead[hslot] = c.psi_of(hc);
             }
         }
-        if (active) rn[tx + 1] = c.psi_of(fb);
+        if (active) ahead[tx + 1] = c.psi_of(fb);
         __syncthreads();
         if (active) {
-            const float *rs = slot(y - y0 - 1), *rc = slot(y - y0);
+            const float *behind = slot(k - 1), *rc = slot(k);
+            const float *rn = dir > 0 ? ahead : behind, *rs = dir > 0 ? behind : ahead;
             const int l = tx + 1;
             const Nb<float> nb = {rc[l], rc[l + 1], rc[l - 1], rn[l], rs[l],
                                   rn[l + 1], rn[l - 1], rs[l - 1], rs[l + 1]};
             float fs[9];
             collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
-            stream_out<R, D>(fout, c, x, y, fs, nt);
+            bstream_out<R, D>(rout, c, x, row(k), fs, nt);
         }
-        if (PF == 2 && halo && more) slot(y - y0 + 2)[hslot] = c.psi_of(hc);
+        if (PF == 2 && halo && more) slot(k + 2)[hslot] = c.psi_of(hc);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             fa[q] = fb[q];
@@ -486,14 +578,28 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
 }
 
 template <typename R, typename D, int SCHEME, int COLL, int PF>
-__global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
-                                                    float *__restrict__ fout,
-                                                    StepConst<R, D> c, int H) {
+__device__ __forceinline__ void sweep_entry(const float *__restrict__ fin, float *__restrict__ fout,
+                                            const StepConst<R, D> &c, int H) {
     extern __shared__ float ring[];  // 4 rows x (TX + 2)
     const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
                           c.flags & kFlagXCD);
     sweep_tile<R, D, SCHEME, COLL, PF>(fin, fout, c, (b % gridDim.x) * blockDim.x,
                                        (b / gridDim.x) * H, H, ring);
+}
+
+template <typename R, typename D, int SCHEME, int COLL, int PF>
+__global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
+                                                    float *__restrict__ fout,
+                                                    StepConst<R, D> c, int H) {
+    sweep_entry<R, D, SCHEME, COLL, PF>(fin, fout, c, H);
+}
+
+// The same kernel asking the register allocator for five waves per SIMD: the mixed-precision
+// and FP32 variants fit without spilling (the FP64 ones would spill, so they use the plain one).
+template <typename R, typename D, int SCHEME, int COLL, int PF>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5, 8)))
+sweep_kernel_w5(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H) {
+    sweep_entry<R, D, SCHEME, COLL, PF>(fin, fout, c, H);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -893,6 +999,7 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.pitch = p.pitch;
     c.frow = p.frow;
     c.fq = p.fq;
+    c.fbytes = (unsigned)pop_bytes(p);
     c.flags = flags;
     c.bq = (D)p.b_quarter;
     c.RT = (D)p.RT;
@@ -966,10 +1073,17 @@ hipError_t sweep_dispatch(const Physics &p, const Launch &L, const float *fin, f
     const StepConst<R, D> c = make_const<R, D>(p, L.flags);
     const dim3 grid((unsigned)((p.nx + L.tx - 1) / L.tx), (unsigned)((p.ny + L.ty - 1) / L.ty));
     const size_t lds = 4 * (size_t)(L.tx + 2) * sizeof(float);
-    if (L.flags & kFlagShallow)
-        PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF1, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
-    else
-        PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF2, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+    if constexpr (sizeof(R) == 8) {
+        if (L.flags & kFlagShallow)
+            PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF1, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+        else
+            PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF2, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+    } else {
+        if (L.flags & kFlagShallow)
+            PPLBM_DISPATCH_X(sweep_kernel_w5, R, D, PPLBM_PF1, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+        else
+            PPLBM_DISPATCH_X(sweep_kernel_w5, R, D, PPLBM_PF2, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+    }
     return hipGetLastError();
 }
 
