@@ -48,22 +48,30 @@ extern "C" {
 #define LBM_ESTATE (-6)        /* call out of order (e.g. step before init)              */
 
 /* ---- physics parameters ----------------------------------------------------------------- */
-enum { LBM_EOS_CARNAHAN_STARLING = 0 };
-enum { LBM_FORCE_EDM = 0, LBM_FORCE_GUO = 1, LBM_FORCE_GUO_LI = 2 };
+enum { LBM_EOS_CARNAHAN_STARLING = 0, LBM_EOS_SBRAGAGLIA_SHAN = 1 };
+enum { LBM_FORCE_EDM = 0, LBM_FORCE_GUO = 1, LBM_FORCE_GUO_LI = 2, LBM_FORCE_SC = 3 };
 enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 /* Arithmetic precision of the kernels; the populations are stored in FP32 either way. */
 enum { LBM_PREC_F32 = 0, LBM_PREC_F64 = 1, LBM_PREC_MIXED = 2 };
 /* Population layout in device memory (see lbm_strides). */
 enum { LBM_LAYOUT_PLANES = 0, LBM_LAYOUT_ROWS = 1 };
 
-/* Equation of state, Eq. 29-30: p = K (rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3 - a rho^2),
- * eta = b rho / 4.  T is given relative to the exact critical temperature of Eq. 29
- * (dp/drho = d2p/drho2 = 0).  Paper values: a = 1, b = 4, R = 1 (Sec. 4.1). */
+/* Equation of state and effective density.
+ * LBM_EOS_CARNAHAN_STARLING, Eq. 29-30: p = K (rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3
+ *   - a rho^2), eta = b rho / 4, and psi from Eq. 7.  T is given relative to the exact critical
+ *   temperature of Eq. 29 (dp/drho = d2p/drho2 = 0).  Paper values: a = 1, b = 4, R = 1
+ *   (Sec. 4.1).  eps is ignored.
+ * LBM_EOS_SBRAGAGLIA_SHAN, Eq. 33: psi = exp(-1/rho) for eps = 0, (rho / (1 + rho))^(1/eps)
+ *   otherwise (eps > 0); the pressure is the one Eq. 7 implies, p0 = rho/3 + G psi^2 / 2, so the
+ *   interaction strength G of lbm_force plays the role of temperature.  a, b, R, T_over_Tc and K
+ *   are ignored.  With the hybrid force, A = -eps/2 makes the mechanical condition (Eq. 18)
+ *   coincide with the Maxwell rule (Eq. 19). */
 typedef struct {
-    int kind;          /* LBM_EOS_CARNAHAN_STARLING */
+    int kind;          /* LBM_EOS_CARNAHAN_STARLING or LBM_EOS_SBRAGAGLIA_SHAN */
     double a, b, R;
     double T_over_Tc;  /* reduced temperature, 0 < T/Tc < 1 for two phases */
     double K;          /* EOS rescale of Eq. 30, K > 0 */
+    double eps;        /* Eq. 33 exponent (LBM_EOS_SBRAGAGLIA_SHAN), >= 0 */
 } lbm_eos;
 
 /* Interaction force and forcing scheme.
@@ -71,7 +79,8 @@ typedef struct {
  *   U = G psi^2 / 2, w(1) = 1/3, w(2) = 1/12 (Eq. 4-6).  psi from p0 = rho/3 + G psi^2/2
  *   (Eq. 7), so G must be negative; the force does not depend on G except through Li's term.
  * scheme: LBM_FORCE_EDM (Eq. 22), LBM_FORCE_GUO (Eq. 23), LBM_FORCE_GUO_LI (Eq. 31: Guo's
- * term with v' = v + sigma F / ((tau - 1/2) psi^2); Eq. 32 gives eps = 16 sigma for G = -1). */
+ * term with v' = v + sigma F / ((tau - 1/2) psi^2); Eq. 32 gives eps = 16 sigma for G = -1),
+ * LBM_FORCE_SC (Eq. 20-21: BGK towards f^eq(rho, u + tau F / rho), no source term; BGK only). */
 typedef struct {
     int scheme;
     double A;      /* Kupershtokh hybrid weight; A = 0 is Eq. 4, A = 1 is Eq. 5 */
@@ -329,8 +338,26 @@ int lbm_eos_critical(const lbm_eos *eos, double *rho_c, double *T_c, double *p_c
 
 /* Maxwell equal-area coexistence densities (Eq. 19) at eos->T_over_Tc; independent of K
  * (Sec. 4.1).  Solved as equal pressure and equal chemical potential of the two phases with
- * the Carnahan-Starling free energy. */
+ * the Carnahan-Starling free energy.  Carnahan-Starling only (LBM_EINVAL otherwise). */
 int lbm_eos_maxwell(const lbm_eos *eos, double *rho_g, double *rho_l);
+
+/* Coexistence densities of a flat interface for either EOS kind (host only).
+ *   LBM_COEX_MAXWELL:    Eq. 19, p0(rho_g) = p0(rho_l) = p_c and the integral of
+ *                        (p_c - p0) / rho^2 over [rho_g, rho_l] vanishes;
+ *   LBM_COEX_MECHANICAL: Eq. 18, the same with the weight psi' / psi^(1 + eps_mech), psi from
+ *                        Eq. 7 (Carnahan-Starling, where G only scales psi) or Eq. 33.
+ * eps_mech is the exponent of Eq. 18 (eps = -2A for the hybrid force of Eq. 6, Table 1;
+ * Eq. 32 for Li's model); ignored by LBM_COEX_MAXWELL.  For the Eq. 33 kind p0 = rho/3 +
+ * G psi^2 / 2, so force->G matters.  Spinodals by a scan of dp0/drho and bisection, branch
+ * densities by bisection, the integral by composite Gauss-Legendre in ln(rho), p_c by
+ * bisection.  LBM_EINVAL for bad arguments or when p0 has no van der Waals loop. */
+enum { LBM_COEX_MAXWELL = 0, LBM_COEX_MECHANICAL = 1 };
+
+/* Bulk pressure p0(rho) (host): Eq. 30 for the Carnahan-Starling kind, rho/3 + G psi^2 / 2 with
+ * psi of Eq. 33 for the other (Eq. 7).  Used for Laplace's law on bubbles (Table 3). */
+int lbm_eos_pressure(const lbm_eos *eos, const lbm_force *force, double rho, double *p);
+int lbm_coexistence(const lbm_eos *eos, const lbm_force *force, int rule, double eps_mech,
+                    double *rho_g, double *rho_l);
 
 /* ---- error text ----------------------------------------------------------------------------- */
 const char *lbm_strerror(int code);

@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
                 ("T", ctypes.c_double), ("K", ctypes.c_double), ("G", ctypes.c_double),
                 ("A", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
                 ("scheme", ctypes.c_int), ("collision", ctypes.c_int),
-                ("s", ctypes.c_double * 9)]
+                ("s", ctypes.c_double * 9),
+                ("psi_kind", ctypes.c_int), ("psi_eps", ctypes.c_double)]
 
 
 _lib = None
@@ -112,11 +113,13 @@ class Params:
     A: float = 0.0
     sigma: float = 0.0
     s: tuple = field(default_factory=lambda: (1.0,) * 9)
+    psi_kind: int = 0     # 0: psi from the EOS (Eq. 7); 1: psi of Eq. 33
+    psi_eps: float = 1.0  # Eq. 33 exponent (psi_kind 1)
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.a, self.b, self.R, self.T, self.K, self.G,
                        self.A, self.sigma, self.tau, self.scheme, self.collision,
-                       (ctypes.c_double * 9)(*self.s))
+                       (ctypes.c_double * 9)(*self.s), self.psi_kind, self.psi_eps)
 
 
 def _ptr(a: np.ndarray):

@@ -69,15 +69,21 @@ def guo_term(F, V):
 
 
 def step(f, nx, ny, T, tau, scheme, collision, a=1.0, b=4.0, R=1.0, K=1.0, G=-1.0, A=0.0,
-         sigma=0.0, s=(1.0,) * 9):
+         sigma=0.0, s=(1.0,) * 9, ss_eps=None):
     """One time step; f is indexed f[alpha][y][x] (nested lists or an array).
-    scheme: 'EDM', 'GUO', 'GUO_LI', 'SC'; collision: 'BGK' or 'MRT'."""
+    scheme: 'EDM', 'GUO', 'GUO_LI', 'SC'; collision: 'BGK' or 'MRT'.
+    ss_eps: None for psi from the EOS (Eq. 7), else the exponent of Eq. 33's psi."""
     nodes = [(x, y) for y in range(ny) for x in range(nx)]
     rho = {n: sum(f[al][n[1]][n[0]] for al in range(9)) for n in nodes}
     psi = {}
     for n in nodes:
-        U = pressure(rho[n], T, a, b, R, K) - CS2 * rho[n]  # Eq. 7
-        psi[n] = math.sqrt(2 * U / G)
+        if ss_eps is None:
+            U = pressure(rho[n], T, a, b, R, K) - CS2 * rho[n]  # Eq. 7
+            psi[n] = math.sqrt(2 * U / G)
+        elif ss_eps == 0:
+            psi[n] = math.exp(-1.0 / rho[n])                      # Eq. 33, eps = 0
+        else:
+            psi[n] = (rho[n] / (1.0 + rho[n])) ** (1.0 / ss_eps)   # Eq. 33
     F = {}
     for (x, y) in nodes:
         Fx = Fy = 0.0

@@ -64,6 +64,8 @@ typedef struct {
     int scheme;     /* ORC_EDM / ORC_GUO / ORC_GUO_LI / ORC_SC */
     int collision;  /* ORC_BGK / ORC_MRT */
     double s[Q];    /* MRT rates, Eq. 35 order (rho, e, eps, jx, qx, jy, qy, pxx, pxy) */
+    int psi_kind;   /* 0: psi from the EOS through Eq. 7; 1: the effective density of Eq. 33 */
+    double psi_eps; /* Eq. 33 exponent eps (psi_kind 1); eps = 0 selects exp(-1/rho) */
 } orc_params;
 
 /* Interaction weight w(|e|^2) given under Eq. 4: w(1) = 1/3, w(2) = 1/12. */
@@ -88,6 +90,13 @@ double orc_pressure(const orc_params *p, double rho)
  * Returns NaN when the state is outside the EOS (eta >= 1) or the radicand is not positive. */
 double orc_psi(const orc_params *p, double rho)
 {
+    if (p->psi_kind == 1) {
+        /* Eq. 33 (Sbragaglia and Shan): psi = exp(-1/rho) for eps = 0, else
+         * (rho / (1 + rho))^(1/eps); the pressure is then whatever Eq. 7 implies. */
+        if (!(rho > 0.0)) return NAN;
+        if (p->psi_eps == 0.0) return exp(-1.0 / rho);
+        return pow(rho / (1.0 + rho), 1.0 / p->psi_eps);
+    }
     double eta = p->b * rho / 4.0;
     if (!(eta < 1.0) || !(rho > 0.0)) return NAN;
     double U = orc_pressure(p, rho) - CS2 * rho;
@@ -187,7 +196,9 @@ static int check_params(const orc_params *p)
 {
     if (!p || p->nx < 1 || p->ny < 1) return ORC_EINVAL;
     if (!(p->tau > 0.5)) return ORC_EINVAL;
-    if (!(p->G < 0.0) || !(p->b > 0.0) || !(p->K > 0.0) || !(p->T > 0.0)) return ORC_EINVAL;
+    if (!(p->G < 0.0)) return ORC_EINVAL;
+    if (p->psi_kind == 0 && (!(p->b > 0.0) || !(p->K > 0.0) || !(p->T > 0.0))) return ORC_EINVAL;
+    if (p->psi_kind != 0 && (p->psi_kind != 1 || !(p->psi_eps >= 0.0))) return ORC_EINVAL;
     if (p->scheme < ORC_EDM || p->scheme > ORC_SC) return ORC_EINVAL;
     if (p->collision != ORC_BGK && p->collision != ORC_MRT) return ORC_EINVAL;
     if (p->collision == ORC_MRT) {

@@ -12,6 +12,9 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
 * ``mechanical``        the mechanical stability condition Eq. 18 with psi of Eq. 7:
                         integral (p_c - p0) psi' / psi^(1+eps) drho = 0.
 * ``eps_from_A`` etc.   the parameter maps eps = -2a/b with Table 1's (a, b) and Eq. 32.
+* ``ss_psi`` etc.       the effective density of Eq. 33 and the pressure Eq. 7 implies for it,
+                        p0 = rho/3 + G psi^2 / 2, with its Maxwell (Eq. 19) and mechanical
+                        (Eq. 18) coexistence densities.
 
 The root finding and quadrature are library routines (mpmath.findroot, mpmath.quad);
 the bracketing and bisection on p_c are written out.
@@ -167,6 +170,51 @@ def chemical_potential(rho, T, a=1.0, b=4.0, R=1.0, K=1.0):
                         + r * R * T * (4 * (b * r / 4) - 3 * (b * r / 4) ** 2)
                         / (1 - b * r / 4) ** 2 - a * r**2)
     return mp.diff(fv, rho)
+
+
+# ---- Eq. 33 (Sbragaglia-Shan effective density) ---------------------------------------
+
+def ss_psi(rho, eps):
+    """psi = exp(-1/rho) for eps = 0, (rho / (1 + rho))^(1/eps) otherwise (Eq. 33)."""
+    rho = mp.mpf(rho)
+    if eps == 0:
+        return mp.exp(-1 / rho)
+    return (rho / (1 + rho)) ** (1 / mp.mpf(eps))
+
+
+def ss_dpsi(rho, eps):
+    """d psi / d rho of Eq. 33: psi / rho^2 (eps = 0), psi / (eps rho (1 + rho)) otherwise."""
+    rho = mp.mpf(rho)
+    if eps == 0:
+        return ss_psi(rho, eps) / rho**2
+    return ss_psi(rho, eps) / (mp.mpf(eps) * rho * (1 + rho))
+
+
+def ss_pressure(rho, eps, G):
+    """The pressure Eq. 7 implies for psi of Eq. 33: rho/3 + G psi^2 / 2."""
+    return mp.mpf(rho) / 3 + mp.mpf(G) * ss_psi(rho, eps) ** 2 / 2
+
+
+def _ss_rho_max(eps, G):
+    # psi -> 1, p0 -> rho/3 + G/2 as rho -> infinity: the loop lies well below rho = -3G.
+    return mp.mpf(-6) * G + 4
+
+
+@lru_cache(maxsize=None)
+def ss_maxwell(eps, G):
+    """(rho_g, rho_l, p_c) of the Maxwell rule (Eq. 19) for the pressure implied by Eq. 33."""
+    p = lambda r: ss_pressure(r, eps, G)
+    dp = lambda r: mp.mpf(1) / 3 + G * ss_psi(r, eps) * ss_dpsi(r, eps)
+    return _coexistence(p, dp, lambda r: 1 / r**2, _ss_rho_max(eps, G))
+
+
+@lru_cache(maxsize=None)
+def ss_mechanical(eps_mech, eps, G):
+    """(rho_g, rho_l, p_c) of Eq. 18 with exponent eps_mech for psi of Eq. 33 (exponent eps)."""
+    p = lambda r: ss_pressure(r, eps, G)
+    dp = lambda r: mp.mpf(1) / 3 + G * ss_psi(r, eps) * ss_dpsi(r, eps)
+    w = lambda r: ss_dpsi(r, eps) / ss_psi(r, eps) ** (1 + mp.mpf(eps_mech))
+    return _coexistence(p, dp, w, _ss_rho_max(eps, G))
 
 
 # ---- parameter maps ------------------------------------------------------------------

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpplbm.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp", "lbm_tune.cpp", "lbm_mlp.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp", "lbm_tune.cpp", "lbm_thermo.cpp", "lbm_mlp.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -186,16 +186,22 @@ int validate(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     if (nx < 1 || ny < 1) return bad("nx and ny must be >= 1");
     if ((double)nx * (double)ny > 4.0e9) return bad("lattice too large");
     if (!(tau > 0.5) || !std::isfinite(tau)) return bad("tau must be > 1/2");
-    if (eos->kind != LBM_EOS_CARNAHAN_STARLING) return bad("unknown EOS kind");
-    if (!(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0) || !(eos->K > 0))
-        return bad("EOS constants a, b, R, K must be positive");
-    if (!(eos->T_over_Tc > 0) || !std::isfinite(eos->T_over_Tc)) return bad("T/Tc must be positive");
+    if (eos->kind == LBM_EOS_CARNAHAN_STARLING) {
+        if (!(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0) || !(eos->K > 0))
+            return bad("EOS constants a, b, R, K must be positive");
+        if (!(eos->T_over_Tc > 0) || !std::isfinite(eos->T_over_Tc)) return bad("T/Tc must be positive");
+    } else if (eos->kind == LBM_EOS_SBRAGAGLIA_SHAN) {
+        if (!(eos->eps >= 0) || !std::isfinite(eos->eps)) return bad("Eq. 33 exponent eps must be >= 0");
+    } else {
+        return bad("unknown EOS kind");
+    }
     if (!(force->G < 0)) return bad("G must be negative (Eq. 7 needs 2 U / G > 0)");
-    if (force->scheme < LBM_FORCE_EDM || force->scheme > LBM_FORCE_GUO_LI) return bad("unknown forcing scheme");
+    if (force->scheme < LBM_FORCE_EDM || force->scheme > LBM_FORCE_SC) return bad("unknown forcing scheme");
     if (!std::isfinite(force->A) || !std::isfinite(force->sigma)) return bad("A and sigma must be finite");
     if (coll->kind != LBM_COLL_BGK && coll->kind != LBM_COLL_MRT) return bad("unknown collision");
     if (coll->kind == LBM_COLL_MRT) {
-        if (force->scheme == LBM_FORCE_EDM) return bad("MRT is defined with Guo's forcing only");
+        if (force->scheme == LBM_FORCE_EDM || force->scheme == LBM_FORCE_SC)
+            return bad("MRT is defined with Guo's forcing only");
         const double r[5] = {coll->s_rho, coll->s_e, coll->s_eps, coll->s_j, coll->s_q};
         for (double s : r)
             if (!(s > 0 && s < 2)) return bad("MRT rates must lie in (0, 2)");
@@ -252,14 +258,21 @@ int ensure_stats(lbm *h) {
 
 namespace pplbm {
 
+void critical_point(double a, double b, double R, double *rho_c, double *T_c, double *p_c) {
+    critical(a, b, R, rho_c, T_c, p_c);
+}
+
 int make_physics(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
                  const lbm_collision *collision, double tau, Physics *out, double *T_out,
                  std::string *why) {
     int rc = validate(nx, ny, eos, force, collision, tau, why);
     if (rc) return rc;
-    double rc_, Tc, pc;
-    critical(eos->a, eos->b, eos->R, &rc_, &Tc, &pc);
-    const double T = eos->T_over_Tc * Tc;
+    double T = 0.0;
+    if (eos->kind == LBM_EOS_CARNAHAN_STARLING) {
+        double rc_, Tc, pc;
+        critical(eos->a, eos->b, eos->R, &rc_, &Tc, &pc);
+        T = eos->T_over_Tc * Tc;
+    }
     Physics p{};
     p.nx = nx;
     p.ny = ny;
@@ -275,6 +288,8 @@ int make_physics(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     p.A = force->A;
     p.sigma = force->scheme == LBM_FORCE_GUO_LI ? force->sigma : 0.0;
     p.tau = tau;
+    p.psi_kind = eos->kind == LBM_EOS_SBRAGAGLIA_SHAN ? 1 : 0;
+    p.inv_eps = (p.psi_kind == 1 && eos->eps > 0) ? 1.0 / eos->eps : 0.0;
     p.scheme = force->scheme;
     p.coll = collision->kind;
     const double snu = 1.0 / tau;
@@ -444,7 +459,7 @@ int lbm_init(lbm_t *h, const double *rho0, const double *u0) {
     if (!h || !rho0) return LBM_EINVAL;
     const size_t N = (size_t)h->p.nx * h->p.ny;
     for (size_t k = 0; k < N; ++k) {
-        const double eta = h->eos.b * rho0[k] / 4.0;
+        const double eta = h->p.psi_kind == 0 ? h->eos.b * rho0[k] / 4.0 : 0.0;  // C-S packing limit
         if (!(rho0[k] > 0) || !(eta < 1)) return fail(h, LBM_EUNSTABLE, "initial density outside (0, 4/b)");
         if (u0 && (!std::isfinite(u0[2 * k]) || !std::isfinite(u0[2 * k + 1])))
             return fail(h, LBM_EINVAL, "non-finite initial velocity");
@@ -706,13 +721,15 @@ int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps) {
 }
 
 int lbm_eos_critical(const lbm_eos *eos, double *rho_c, double *T_c, double *p_c) {
-    if (!eos || !(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
+    if (!eos || eos->kind != LBM_EOS_CARNAHAN_STARLING) return LBM_EINVAL;
+    if (!(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
     critical(eos->a, eos->b, eos->R, rho_c, T_c, p_c);
     return LBM_OK;
 }
 
 int lbm_eos_maxwell(const lbm_eos *eos, double *rho_g, double *rho_l) {
-    if (!eos || !rho_g || !rho_l || !(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
+    if (!eos || eos->kind != LBM_EOS_CARNAHAN_STARLING) return LBM_EINVAL;
+    if (!rho_g || !rho_l || !(eos->a > 0) || !(eos->b > 0) || !(eos->R > 0)) return LBM_EINVAL;
     if (!(eos->T_over_Tc > 0 && eos->T_over_Tc < 1)) return LBM_EINVAL;
     return maxwell(*eos, rho_g, rho_l);
 }

@@ -274,7 +274,7 @@ int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0) 
     const Physics &p = b->phys[i];
     const size_t N = (size_t)p.nx * p.ny;
     for (size_t k = 0; k < N; ++k)
-        if (!(rho0[k] > 0) || !(p.b_quarter * rho0[k] < 1))
+        if (!(rho0[k] > 0) || (p.psi_kind == 0 && !(p.b_quarter * rho0[k] < 1)))
             return bfail(b, LBM_EUNSTABLE, "initial density outside (0, 4/b)");
     double *d = nullptr;
     if (hipMalloc(&d, N * sizeof(double) * (u0 ? 3 : 1)) != hipSuccess) {
@@ -384,7 +384,7 @@ int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double 
         }
     }
     if (e == hipSuccess && rc == LBM_OK) e = measure(stretch, &m);
-    if (e == hipSuccess && rc == LBM_OK && !(lo_rho > 0 && p.b_quarter * hi_rho < 1))
+    if (e == hipSuccess && rc == LBM_OK && !(lo_rho > 0 && (p.psi_kind != 0 || p.b_quarter * hi_rho < 1)))
         rc = bfail(b, LBM_EUNSTABLE, "profile density outside (0, 4/b)");
     if (e == hipSuccess && rc == LBM_OK) e = pplbm::launch_profile_init(p, log_rho, R, stretch, b->f0[i], b->stream);
     if (e == hipSuccess && rc == LBM_OK) e = hipStreamSynchronize(b->stream);

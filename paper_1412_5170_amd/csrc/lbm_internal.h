@@ -11,7 +11,7 @@
 
 namespace pplbm {
 
-enum Scheme { EDM = 0, GUO = 1, GUO_LI = 2 };
+enum Scheme { EDM = 0, GUO = 1, GUO_LI = 2, SC = 3 };
 enum Coll { BGK = 0, MRT = 1 };
 
 // Everything a step needs, in FP64; the launchers convert to the kernels' arithmetic type.
@@ -29,6 +29,8 @@ struct Physics {
     double A;           // hybrid weight             (Eq. 6)
     double sigma;       // Li's constant             (Eq. 31)
     double tau;         // relaxation time           (Eq. 1)
+    int psi_kind;       // 0: psi from the EOS (Eq. 7); 1: psi of Eq. 33
+    double inv_eps;     // Eq. 33: 1/eps, 0 for the exp(-1/rho) form
     double s[9];        // MRT rates, moment order (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
     int scheme, coll;
 };
@@ -114,6 +116,9 @@ hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblock
 // through 32-bit buffer offsets, so it needs this below 4 GiB.
 inline size_t pop_bytes(const Physics &p) { return 9 * p.plane * sizeof(float); }
 constexpr size_t kSweepMaxBytes = 0xFFFFFFFFull;
+
+// Exact critical point of Eq. 29 (dp/drho = d2p/drho2 = 0), host.
+void critical_point(double a, double b, double R, double *rho_c, double *T_c, double *p_c);
 
 // Autotuner cache (JSON lines; see lbm_tune.cpp).
 std::string device_tag();

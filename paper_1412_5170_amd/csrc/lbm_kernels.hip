@@ -84,6 +84,15 @@ __device__ __forceinline__ T eos_psi(T rho, T bq, T RT, T a, T K, T two_over_G) 
     return r > T(0) ? T(__builtin_amdgcn_sqrtf((float)r)) : qnan<T>();
 }
 
+// Effective density of Eq. 33 (Sbragaglia-Shan): exp(-1/rho) for eps = 0 (inv_eps = 0 flags
+// it), (rho / (1 + rho))^(1/eps) otherwise.  The EOS is then the one Eq. 7 implies.
+template <typename T>
+__device__ __forceinline__ T ss_psi(T rho, T inv_eps) {
+    if (!(rho > T(0))) return qnan<T>();
+    if (inv_eps == T(0)) return exp(-T(1) / rho);
+    return exp(inv_eps * log(rho / (T(1) + rho)));
+}
+
 // ---------------------------------------------------------------------------------------
 // Constants of a step, converted once on the host.
 // ---------------------------------------------------------------------------------------
@@ -95,6 +104,9 @@ struct StepConst {
     unsigned fbytes;   // bytes of one population buffer (the one-pass sweep needs < 4 GiB)
     int flags;         // kFlagNT | kFlagXCD
     D bq, RT, a, K, two_over_G;  // EOS (Eq. 29-30) and Eq. 7
+    int psi_kind;     // 0: psi from the C-S EOS through Eq. 7; 1: psi of Eq. 33
+    D inv_eps;        // Eq. 33 exponent 1/eps (0: the exp(-1/rho) branch)
+    D tau;            // relaxation time (Shan-Chen velocity shift, Eq. 21)
     D gA;     // -G A / 2        coefficient of sum w psi^2 e    (Eq. 6, U = G psi^2 / 2)
     D gB;     // -G (1 - A)      coefficient of psi(x) sum w psi e
     D omega;  // 1 / tau
@@ -106,7 +118,10 @@ struct StepConst {
     R lim[9]; // 1 / (1/s_k - 1/2) for the moments that carry Li's stress
 
     __device__ __forceinline__ float psi_of(const float f[9]) const {
-        return (float)eos_psi<D>(density9<D>(f), bq, RT, a, K, two_over_G);
+        const D rho = density9<D>(f);
+        if (psi_kind == 0) return (float)eos_psi<D>(rho, bq, RT, a, K, two_over_G);
+        // Eq. 33 in the shape precision R (FP32 in the mixed path): psi is stored in FP32.
+        return (float)ss_psi<R>((R)rho, (R)inv_eps);
     }
 };
 
@@ -221,6 +236,12 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
                 const R shape = R(3) * eD[q] + R(4.5) * eD[q] * eS[q] - DS;
                 upd[q] = c.omega * neq[q] + wgt<D>(q) * rho_d * (D)shape;
             }
+        } else if constexpr (SCHEME == SC) {
+            // Eq. 20-21: BGK towards f^eq(rho, u + tau F / rho), no source term.
+            const R ex = (R)(uxd + c.tau * Fxd * inv), ey = (R)(uyd + c.tau * Fyd * inv);
+            eq_minus_f<R, D>(rho_d, ex, ey, f, neq);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) upd[q] = c.omega * neq[q];
         } else {
             // Eq. 23 (Guo) or Eq. 31 (Li): equilibrium at v, bracket at v or v'.
             eq_minus_f<R, D>(rho_d, vx, vy, f, neq);
@@ -639,6 +660,9 @@ __global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchLattice *__
         case GUO_LI * 2 + BGK:
             sweep_tile<float, double, GUO_LI, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
             break;
+        case SC * 2 + BGK:
+            sweep_tile<float, double, SC, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
+            break;
         case GUO * 2 + MRT:
             sweep_tile<float, double, GUO, MRT, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
             break;
@@ -1006,6 +1030,9 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.a = (D)p.a;
     c.K = (D)p.K;
     c.two_over_G = (D)(2.0 / p.G);
+    c.psi_kind = p.psi_kind;
+    c.inv_eps = (D)p.inv_eps;
+    c.tau = (D)p.tau;
     c.gA = (D)(-p.G * p.A / 2.0);
     c.gB = (D)(-p.G * (1.0 - p.A));
     c.omega = (D)(1.0 / p.tau);
@@ -1033,6 +1060,8 @@ dim3 row_grid(int nx, int ny, int block) {
                 hipLaunchKernelGGL((KERNEL<R, D, EDM, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
             else if ((p).scheme == GUO)                                                         \
                 hipLaunchKernelGGL((KERNEL<R, D, GUO, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
+            else if ((p).scheme == SC)                                                          \
+                hipLaunchKernelGGL((KERNEL<R, D, SC, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);     \
             else                                                                                \
                 hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__); \
         } else {                                                                                \

@@ -16,21 +16,24 @@ LIB_PATH = os.path.join(_HERE, "libpplbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ENOTCONVERGED, LBM_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
-LBM_EOS_CARNAHAN_STARLING = 0
-LBM_FORCE_EDM, LBM_FORCE_GUO, LBM_FORCE_GUO_LI = 0, 1, 2
+LBM_EOS_CARNAHAN_STARLING, LBM_EOS_SBRAGAGLIA_SHAN = 0, 1
+LBM_FORCE_EDM, LBM_FORCE_GUO, LBM_FORCE_GUO_LI, LBM_FORCE_SC = 0, 1, 2, 3
+LBM_COEX_MAXWELL, LBM_COEX_MECHANICAL = 0, 1
 LBM_COLL_BGK, LBM_COLL_MRT = 0, 1
 LBM_PREC_F32, LBM_PREC_F64, LBM_PREC_MIXED = 0, 1, 2
 LBM_LAYOUT_PLANES, LBM_LAYOUT_ROWS = 0, 1
 LBM_KERNEL_TWO_PASS, LBM_KERNEL_SWEEP = 0, 1
 LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_XCD_ORDER, LBM_LAUNCH_SHALLOW = 1, 2, 4
 
-SCHEMES = {"EDM": LBM_FORCE_EDM, "GUO": LBM_FORCE_GUO, "GUO_LI": LBM_FORCE_GUO_LI}
+SCHEMES = {"EDM": LBM_FORCE_EDM, "GUO": LBM_FORCE_GUO, "GUO_LI": LBM_FORCE_GUO_LI,
+           "SC": LBM_FORCE_SC}
 COLLISIONS = {"BGK": LBM_COLL_BGK, "MRT": LBM_COLL_MRT}
 
 
 class lbm_eos(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("a", ctypes.c_double), ("b", ctypes.c_double),
-                ("R", ctypes.c_double), ("T_over_Tc", ctypes.c_double), ("K", ctypes.c_double)]
+                ("R", ctypes.c_double), ("T_over_Tc", ctypes.c_double), ("K", ctypes.c_double),
+                ("eps", ctypes.c_double)]
 
 
 class lbm_force(ctypes.Structure):
@@ -94,6 +97,10 @@ _SIG = {
     "lbm_timing": (ctypes.c_int, [_P, _D, _D, ctypes.POINTER(ctypes.c_longlong)]),
     "lbm_eos_critical": (ctypes.c_int, [ctypes.POINTER(lbm_eos), _D, _D, _D]),
     "lbm_eos_maxwell": (ctypes.c_int, [ctypes.POINTER(lbm_eos), _D, _D]),
+    "lbm_eos_pressure": (ctypes.c_int, [ctypes.POINTER(lbm_eos), ctypes.POINTER(lbm_force),
+                                        ctypes.c_double, _D]),
+    "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_eos), ctypes.POINTER(lbm_force),
+                                       ctypes.c_int, ctypes.c_double, _D, _D]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
     "lbm_copy_f32": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
@@ -126,7 +133,13 @@ def _dptr(a):
 
 
 def make_eos(T_over_Tc, K=1.0, a=1.0, b=4.0, R=1.0):
-    return lbm_eos(LBM_EOS_CARNAHAN_STARLING, a, b, R, T_over_Tc, K)
+    """Carnahan-Starling EOS (Eq. 29-30) at T/Tc, psi from Eq. 7."""
+    return lbm_eos(LBM_EOS_CARNAHAN_STARLING, a, b, R, T_over_Tc, K, 0.0)
+
+
+def make_ss_eos(eps):
+    """Effective density of Eq. 33 with exponent eps (0: exp(-1/rho)); pressure from Eq. 7."""
+    return lbm_eos(LBM_EOS_SBRAGAGLIA_SHAN, 1.0, 4.0, 1.0, 0.5, 1.0, eps)
 
 
 def make_force(scheme="GUO", A=0.0, sigma=0.0, G=-1.0):
@@ -142,6 +155,23 @@ def eos_critical(eos: lbm_eos):
     rc, Tc, pc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     check(lbm_eos_critical(ctypes.byref(eos), ctypes.byref(rc), ctypes.byref(Tc), ctypes.byref(pc)))
     return rc.value, Tc.value, pc.value
+
+
+def coexistence(eos: lbm_eos, force: lbm_force, rule="maxwell", eps_mech=0.0):
+    """Flat-interface coexistence densities (rho_g, rho_l): rule 'maxwell' (Eq. 19) or
+    'mechanical' (Eq. 18 with exponent eps_mech)."""
+    g, l = ctypes.c_double(), ctypes.c_double()
+    r = LBM_COEX_MAXWELL if rule == "maxwell" else LBM_COEX_MECHANICAL
+    check(lbm_coexistence(ctypes.byref(eos), ctypes.byref(force), r, float(eps_mech),
+                          ctypes.byref(g), ctypes.byref(l)))
+    return g.value, l.value
+
+
+def eos_pressure(eos: lbm_eos, force: lbm_force, rho):
+    """Bulk pressure p0(rho) of the EOS (Eq. 30, or Eq. 7 with Eq. 33's psi)."""
+    p = ctypes.c_double()
+    check(lbm_eos_pressure(ctypes.byref(eos), ctypes.byref(force), float(rho), ctypes.byref(p)))
+    return p.value
 
 
 def eos_maxwell(eos: lbm_eos):
@@ -291,16 +321,19 @@ def bcheck(code, b=None):
 
 class Batch:
     """Independent lattices advanced together (lbm_batch_*).  members: list of dicts with nx,
-    ny, T_over_Tc, K, scheme, A, sigma, collision, s (5 MRT rates), tau."""
+    ny, T_over_Tc, K, scheme, A, sigma, collision, s (5 MRT rates), tau; "psi_eps" (with "G")
+    selects the effective density of Eq. 33 instead of the Carnahan-Starling EOS."""
 
     def __init__(self, members, tx=128, groups=0, flags=LBM_LAUNCH_SHALLOW):
         n = len(members)
         self.members = members
         nx = (ctypes.c_int * n)(*[m["nx"] for m in members])
         ny = (ctypes.c_int * n)(*[m["ny"] for m in members])
-        eos = (lbm_eos * n)(*[make_eos(m["T_over_Tc"], K=m.get("K", 1.0)) for m in members])
+        eos = (lbm_eos * n)(*[make_ss_eos(m["psi_eps"]) if "psi_eps" in m else
+                              make_eos(m["T_over_Tc"], K=m.get("K", 1.0)) for m in members])
         frc = (lbm_force * n)(*[make_force(m.get("scheme", "GUO"), A=m.get("A", 0.0),
-                                           sigma=m.get("sigma", 0.0)) for m in members])
+                                           sigma=m.get("sigma", 0.0), G=m.get("G", -1.0))
+                                for m in members])
         col = (lbm_collision * n)(*[make_collision(m.get("collision", "BGK"),
                                                    s=m.get("s", (1.0, 1.1, 1.1, 1.0, 1.1)))
                                     for m in members])

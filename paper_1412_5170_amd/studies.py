@@ -1,0 +1,234 @@
+"""The paper's numerical experiments (Sec. 4) as batched GPU jobs on the library.
+
+Every study builds its lattices as members of one `Batch`, starts each at physical rest
+(`init_rest`: f = f^eq(rho0, -F/(2 rho0)), so v = 0), runs the batch until every member's
+velocity field and probe densities stop changing, and reads FP64 observables (`Batch.stats`:
+probe densities, max |v|).  Reference coexistence densities come from the library's own
+solver of Eq. 18 / Eq. 19 (`lbm.coexistence`).
+
+* `tau_sweep`        Sec. 4.2.1, Fig. 2: gas density of a flat interface against tau for the
+                     Shan-Chen (Eq. 20-21), EDM (Eq. 22) and Guo (Eq. 23) schemes, Table 2's
+                     force (A = -0.26, eps = 0.52, K = 1); SC and EDM coincide at tau = 1.
+* `ratio_vs_T`       Figs. 3-4: density ratio of a flat interface against T/Tc for tau = 0.7
+                     and 1.5, EDM (A = -0.26) and Guo (A = -0.5).
+* `coexistence`      Fig. 5 (EDM and Guo, eps = 0.52, against the mechanical solution), Fig. 6
+                     (modified Kupershtokh, A = -0.84, and Li, sigma = 0.105, both eps = 1.68,
+                     against the mechanical and Maxwell solutions) and Table 6 (K = 1,
+                     eps = 1.68 and K = 0.1, eps = 2 at T = 0.6 Tc).
+* `eq33`             Sec. 4.3.1: with psi of Eq. 33 and the matching A = -eps/2 a flat
+                     interface settles near the Maxwell densities of the implied EOS (within
+                     0.6 % for G = -2.6, eps = 1); thinner interfaces (stronger |G|) drift
+                     further, and at G = -3 the interface no longer settles.
+* `bubbles`          Tables 3, 4, 5 and 7: a bubble of radius 23 in a 100 x 100 box at
+                     T = 0.6 Tc; rho_l, rho_g, Us_max and (Table 3) the surface tension from
+                     Laplace's law with the equimolar radius.
+
+    python -m paper_1412_5170_amd.studies bubbles --out bubbles.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import inputs
+
+SLAB_NY = 256          # flat interfaces: a 4 x 256 column, liquid in rows [64, 192)
+BUBBLE_N, BUBBLE_R = 100, 23.0
+MRT_RATES = (1.0, 1.1, 1.1, 1.0, 1.1)   # s_rho, s_e, s_eps, s_j, s_q (s_nu = 1/tau)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def slab_member(T_over_Tc, scheme, A=0.0, sigma=0.0, K=1.0, tau=1.0, collision="BGK", **kw):
+    m = dict(nx=4, ny=SLAB_NY, init="slab", T_over_Tc=T_over_Tc, K=K, scheme=scheme, A=A,
+             sigma=sigma, collision=collision, tau=tau, s=MRT_RATES)
+    m.update(kw)
+    return m
+
+
+def bubble_member(scheme, A=0.0, sigma=0.0, K=1.0, tau=1.0, collision="BGK", T_over_Tc=0.6):
+    return dict(nx=BUBBLE_N, ny=BUBBLE_N, init="bubble", R=BUBBLE_R, T_over_Tc=T_over_Tc, K=K,
+                scheme=scheme, A=A, sigma=sigma, collision=collision, tau=tau, s=MRT_RATES)
+
+
+def _eos(lbm, m):
+    if "psi_eps" in m:
+        return lbm.make_ss_eos(m["psi_eps"])
+    return lbm.make_eos(m["T_over_Tc"], K=m["K"])
+
+
+def _force(lbm, m):
+    return lbm.make_force(m["scheme"], A=m.get("A", 0.0), sigma=m.get("sigma", 0.0),
+                          G=m.get("G", -1.0))
+
+
+def initial_density(lbm, m):
+    """Maxwell densities (Eq. 19) in the shape of the member: slab (liquid in the middle half
+    of the rows), bubble (gas inside radius R) or droplet, tanh interfaces of width 5."""
+    g, l = lbm.coexistence(_eos(lbm, m), _force(lbm, m), "maxwell")
+    if m["init"] == "slab":
+        y = np.arange(m["ny"], dtype=np.float64)[:, None] * np.ones((1, m["nx"]))
+        d = np.abs(y + 0.5 - m["ny"] / 2) - m["ny"] / 4      # < 0 inside the liquid layer
+        return (l + g) / 2 - (l - g) / 2 * np.tanh(2 * d / 5.0)
+    if m["init"] == "bubble":
+        return inputs.droplet(m["nx"], m["ny"], m["R"], 5.0, g, l)
+    return inputs.droplet(m["nx"], m["ny"], m["R"], 5.0, l, g)
+
+
+def run(lbm, members, tol=1e-10, tol_rho=1e-10, check_every=1000, max_steps=400_000):
+    """One batch, every member from rest; probes: the slab's middle row and its first row
+    (liquid, gas), the bubble's centre and corner (gas, liquid).  Returns per-member dicts."""
+    b = lbm.Batch(members)
+    for i, m in enumerate(members):
+        b.init_rest(i, initial_density(lbm, m))
+    t0 = time.perf_counter()
+    steps, status = b.run(tol, check_every=check_every, max_steps=max_steps, tol_rho=tol_rho)
+    wall = time.perf_counter() - t0
+    out = []
+    for i, m in enumerate(members):
+        rec = dict(m, steps=int(steps[i]), status=int(status[i]))
+        rho, v = b.read(i)
+        if not np.all(np.isfinite(rho)):
+            rec["unstable"] = True
+            out.append(rec)
+            continue
+        vmag = np.hypot(v[..., 0], v[..., 1])
+        rec["us_max"] = float(vmag.max())
+        if m["init"] == "slab":
+            rec["rho_l"] = float(rho[m["ny"] // 2, 0])
+            rec["rho_g"] = float(rho[0, 0])
+        else:
+            inner = float(rho[m["ny"] // 2, m["nx"] // 2])
+            outer = float(rho[0, 0])
+            rec["rho_g"], rec["rho_l"] = (inner, outer) if m["init"] == "bubble" else (outer, inner)
+            rec.update(_laplace(lbm, m, rho, rec["rho_g"], rec["rho_l"]))
+        out.append(rec)
+    say(f"studies: {len(members)} lattices, {wall:.1f} s, max steps {max(steps)}")
+    return out
+
+
+def _laplace(lbm, m, rho, rho_g, rho_l):
+    """Equimolar radius from the mass and the two bulk densities, pressure jump from the bulk
+    pressures p0(rho) of the EOS, surface tension sigma = R dp (Laplace, 2-D)."""
+    n = m["nx"] * m["ny"]
+    area_inner = (rho.sum() - n * (rho_l if m["init"] == "bubble" else rho_g)) / \
+        ((rho_g - rho_l) if m["init"] == "bubble" else (rho_l - rho_g))
+    R = math.sqrt(max(area_inner, 0.0) / math.pi)
+    e, f = _eos(lbm, m), _force(lbm, m)
+    pin = lbm.eos_pressure(e, f, rho_g if m["init"] == "bubble" else rho_l)
+    pout = lbm.eos_pressure(e, f, rho_l if m["init"] == "bubble" else rho_g)
+    return {"radius": R, "dp": pin - pout, "surface_tension": R * (pin - pout)}
+
+
+# ---- studies ---------------------------------------------------------------------------
+
+def tau_sweep(lbm, T_over_Tc=0.8, taus=(0.6, 0.7, 0.8, 1.0, 1.2, 1.5, 2.0)):
+    members = []
+    for scheme, A in (("SC", -0.26), ("EDM", -0.26), ("GUO", -0.26)):
+        for tau in taus:
+            members.append(slab_member(T_over_Tc, scheme, A=A, tau=tau))
+    return run(lbm, members)
+
+
+def ratio_vs_T(lbm, temps=(0.6, 0.7, 0.8, 0.9), taus=(0.7, 1.5)):
+    members = [slab_member(t, scheme, A=A, tau=tau) for scheme, A in (("EDM", -0.26), ("GUO", -0.5))
+               for t in temps for tau in taus]
+    res = run(lbm, members)
+    for r in res:
+        if "rho_g" in r:
+            r["ratio"] = r["rho_l"] / r["rho_g"]
+    return res
+
+
+def coexistence(lbm, temps=(0.55, 0.6, 0.7, 0.8, 0.9)):
+    """Figs. 5-6 and Table 6 with the library's mechanical (Eq. 18) and Maxwell solutions."""
+    members = []
+    for t in temps:
+        members.append(slab_member(t, "EDM", A=-0.26, study="fig5", eps=0.52))
+        members.append(slab_member(t, "GUO", A=-0.26, study="fig5", eps=0.52))
+        members.append(slab_member(t, "GUO", A=-0.84, study="fig6", eps=1.68))
+        members.append(slab_member(t, "GUO_LI", A=0.0, sigma=0.105, study="fig6", eps=1.68))
+    members.append(slab_member(0.6, "GUO", A=-0.84, K=1.0, study="table6", eps=1.68))
+    members.append(slab_member(0.6, "GUO", A=-1.0, K=0.1, study="table6", eps=2.0))
+    members.append(slab_member(0.6, "GUO_LI", sigma=0.105, K=1.0, study="table6", eps=1.68))
+    members.append(slab_member(0.6, "GUO_LI", sigma=0.125, K=0.1, study="table6", eps=2.0))
+    res = run(lbm, members)
+    for r in res:
+        e, f = _eos(lbm, r), _force(lbm, r)
+        r["maxwell_g"], r["maxwell_l"] = lbm.coexistence(e, f, "maxwell")
+        try:
+            r["mech_g"], r["mech_l"] = lbm.coexistence(e, f, "mechanical", r["eps"])
+        except lbm.LBMError:
+            # Eq. 18 has no root with a positive coexistence pressure (the gas branch
+            # vanishes), e.g. eps = 0.52 at T/Tc <= 0.7
+            r["mech_g"] = r["mech_l"] = None
+    return res
+
+
+def eq33(lbm, cases=((1.0, -2.6), (1.0, -2.8), (0.0, -2.6), (0.0, -2.8))):
+    """Flat interfaces with psi of Eq. 33 and A = -eps/2 (so Eq. 18 is Eq. 19): the densities
+    approach the Maxwell ones of the implied EOS, more closely the wider the interface (the
+    weaker |G|); Guo's forcing, tau = 1 and 0.8."""
+    members = []
+    for eps, G in cases:
+        for tau in (1.0, 0.8):
+            members.append(dict(nx=4, ny=SLAB_NY, init="slab", psi_eps=eps, G=G, A=-eps / 2,
+                                scheme="GUO", collision="BGK", tau=tau, s=MRT_RATES,
+                                T_over_Tc=0.5, K=1.0))
+    res = run(lbm, members)
+    for r in res:
+        f = _force(lbm, r)
+        r["maxwell_g"], r["maxwell_l"] = lbm.coexistence(lbm.make_ss_eos(r["psi_eps"]), f,
+                                                         "maxwell")
+    return res
+
+
+def bubbles(lbm):
+    members = []
+    for scheme, A in (("GUO", -0.45), ("EDM", -0.13)):                        # Table 3
+        for tau in (1.5, 0.7):
+            members.append(dict(bubble_member(scheme, A=A, K=0.5, tau=tau), table=3))
+    for tau in (0.7, 0.8, 1.0, 1.5):                                         # Table 4
+        members.append(dict(bubble_member("GUO", A=-0.84, tau=tau), table=4))
+    for tau in (0.7, 0.8, 1.0, 1.5):                                         # Table 5
+        members.append(dict(bubble_member("GUO_LI", sigma=0.105, tau=tau), table=5))
+    for tau in (0.7, 1.0, 1.5):                                              # Table 7
+        members.append(dict(bubble_member("GUO", A=-0.84, tau=tau, collision="MRT"), table=7))
+    return run(lbm, members, tol=1e-9, tol_rho=1e-9, check_every=500, max_steps=300_000)
+
+
+STUDIES = {"tau": tau_sweep, "ratio": ratio_vs_T, "coexistence": coexistence, "eq33": eq33,
+           "bubbles": bubbles}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=list(STUDIES) + ["all"])
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    from . import lbm
+    names = list(STUDIES) if a.study == "all" else [a.study]
+    out = {}
+    for n in names:
+        say(f"studies: {n}")
+        out[n] = STUDIES[n](lbm)
+        for r in out[n]:
+            keys = ("table", "study", "scheme", "collision", "T_over_Tc", "K", "tau", "psi_eps",
+                    "rho_l", "rho_g", "us_max", "surface_tension", "mech_g", "maxwell_g",
+                    "steps", "status")
+            say("   " + json.dumps({k: (round(r[k], 7) if isinstance(r[k], float) else r[k])
+                                    for k in keys if k in r}))
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(out, fh)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -25,24 +25,37 @@ def workload(name, **over):
 
 
 def oracle_params(wl):
+    """Oracle parameters of a workload; a "psi_eps" key selects the effective density of
+    Eq. 33 (with interaction strength "G") instead of the Carnahan-Starling EOS."""
     tau = wl["tau"]
     s5 = wl.get("s5", MRT_RATES)
     s = (s5[0], s5[1], s5[2], s5[3], s5[4], s5[3], s5[4], 1 / tau, 1 / tau)
-    return O.Params(nx=wl["nx"], ny=wl["ny"], T=TH.temperature(wl["T_over_Tc"]), tau=tau,
-                    scheme=getattr(O, wl["scheme"]), collision=getattr(O, wl["collision"]),
-                    K=wl["K"], A=wl["A"], sigma=wl["sigma"], s=s)
+    extra = {}
+    if "psi_eps" in wl:
+        extra = dict(psi_kind=1, psi_eps=wl["psi_eps"], G=wl["G"])
+    return O.Params(nx=wl["nx"], ny=wl["ny"], T=TH.temperature(wl.get("T_over_Tc", 0.5)),
+                    tau=tau, scheme=getattr(O, wl["scheme"]),
+                    collision=getattr(O, wl["collision"]), K=wl.get("K", 1.0), A=wl["A"],
+                    sigma=wl.get("sigma", 0.0), s=s, **extra)
 
 
 def gpu_lattice(L, wl, precision, tile=None, layout=1):
-    eos = L.make_eos(wl["T_over_Tc"], K=wl["K"])
-    force = L.make_force(wl["scheme"], A=wl["A"], sigma=wl["sigma"])
+    if "psi_eps" in wl:
+        eos = L.make_ss_eos(wl["psi_eps"])
+        force = L.make_force(wl["scheme"], A=wl["A"], sigma=wl.get("sigma", 0.0), G=wl["G"])
+    else:
+        eos = L.make_eos(wl["T_over_Tc"], K=wl["K"])
+        force = L.make_force(wl["scheme"], A=wl["A"], sigma=wl["sigma"])
     coll = L.make_collision(wl["collision"], s=wl.get("s5", MRT_RATES))
     return L.Lattice(wl["nx"], wl["ny"], eos, force, coll, wl["tau"], precision=precision,
                      tile=tile, layout=layout)
 
 
 def initial_density(wl):
-    g, l, _ = TH.maxwell(wl["T_over_Tc"])
+    if "psi_eps" in wl:
+        g, l, _ = TH.ss_maxwell(wl["psi_eps"], wl["G"])
+    else:
+        g, l, _ = TH.maxwell(wl["T_over_Tc"])
     return inputs.initial_density(wl, l, g)
 
 

@@ -88,3 +88,64 @@ def test_binding_has_no_cpu_path():
     for f in os.listdir(os.path.join(ROOT, "paper_1412_5170_amd")):
         if f.endswith(".py"):
             assert "import oracle" not in open(os.path.join(ROOT, "paper_1412_5170_amd", f)).read()
+
+
+# ---- flat-interface coexistence (host) ---------------------------------------------------
+
+@pytest.mark.parametrize("ttc,K,eps", [(0.6, 1.0, 1.68), (0.6, 0.1, 2.0), (0.8, 1.0, 0.52)])
+def test_coexistence_mechanical_matches_oracle(thermo, ttc, K, eps):
+    from paper_1412_5170_amd import lbm
+    g, l = lbm.coexistence(lbm.make_eos(ttc, K=K), lbm.make_force("GUO"), "mechanical", eps)
+    og, ol, _ = thermo.mechanical(ttc, eps, K=K)
+    assert g == pytest.approx(og, rel=1e-11) and l == pytest.approx(ol, rel=1e-11)
+
+
+def test_coexistence_maxwell_matches_oracle(thermo):
+    from paper_1412_5170_amd import lbm
+    for ttc in (0.5, 0.7, 0.9):
+        g, l = lbm.coexistence(lbm.make_eos(ttc), lbm.make_force("GUO"), "maxwell")
+        og, ol, _ = thermo.maxwell(ttc)
+        assert g == pytest.approx(og, rel=1e-11) and l == pytest.approx(ol, rel=1e-11)
+
+
+@pytest.mark.parametrize("eps,G", [(1.0, -3.0), (0.0, -4.0)])
+def test_coexistence_eq33_consistent(thermo, eps, G):
+    """Eq. 33: the mechanical condition with the matching exponent is the Maxwell rule."""
+    from paper_1412_5170_amd import lbm
+    f = lbm.make_force("GUO", G=G)
+    a = lbm.coexistence(lbm.make_ss_eos(eps), f, "maxwell")
+    b = lbm.coexistence(lbm.make_ss_eos(eps), f, "mechanical", eps)
+    o = thermo.ss_maxwell(eps, G)
+    assert a[0] == pytest.approx(o[0], rel=1e-11) and a[1] == pytest.approx(o[1], rel=1e-11)
+    assert b[0] == pytest.approx(a[0], rel=1e-11) and b[1] == pytest.approx(a[1], rel=1e-11)
+
+
+def test_coexistence_rejects_single_phase():
+    from paper_1412_5170_amd import lbm
+    with pytest.raises(lbm.LBMError):
+        lbm.coexistence(lbm.make_ss_eos(1.0), lbm.make_force("GUO", G=-1.0), "maxwell")
+    with pytest.raises(lbm.LBMError):
+        lbm.coexistence(lbm.make_eos(1.2), lbm.make_force("GUO"), "maxwell")
+    with pytest.raises(lbm.LBMError):  # the C-S Maxwell helper does not take Eq. 33
+        lbm.eos_maxwell(lbm.make_ss_eos(1.0))
+
+
+def test_create_accepts_sc_and_eq33_and_rejects_sc_mrt():
+    from paper_1412_5170_amd import lbm
+    ok = lbm.lbm_create
+    import ctypes
+    h = lbm._P()
+    eos, coll = lbm.make_eos(0.7), lbm.make_collision("BGK")
+    assert ok(8, 8, ctypes.byref(eos), ctypes.byref(lbm.make_force("SC")), ctypes.byref(coll),
+              1.0, ctypes.byref(h)) == lbm.LBM_OK
+    lbm.lbm_destroy(h)
+    ss = lbm.make_ss_eos(1.0)
+    assert ok(8, 8, ctypes.byref(ss), ctypes.byref(lbm.make_force("GUO", G=-3.0)),
+              ctypes.byref(coll), 1.0, ctypes.byref(h)) == lbm.LBM_OK
+    lbm.lbm_destroy(h)
+    mrt = lbm.make_collision("MRT")
+    assert ok(8, 8, ctypes.byref(eos), ctypes.byref(lbm.make_force("SC")), ctypes.byref(mrt),
+              1.0, ctypes.byref(h)) == lbm.LBM_EINVAL
+    bad = lbm.make_ss_eos(-1.0)
+    assert ok(8, 8, ctypes.byref(bad), ctypes.byref(lbm.make_force("GUO", G=-3.0)),
+              ctypes.byref(coll), 1.0, ctypes.byref(h)) == lbm.LBM_EINVAL

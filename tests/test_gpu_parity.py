@@ -28,7 +28,8 @@ def L():
 
 
 PRECISIONS = {"f32": 0, "f64": 1, "mixed": 2}
-SCHEMES = [("EDM", "BGK"), ("GUO", "BGK"), ("GUO_LI", "BGK"), ("GUO", "MRT"), ("GUO_LI", "MRT")]
+SCHEMES = [("EDM", "BGK"), ("GUO", "BGK"), ("GUO_LI", "BGK"), ("SC", "BGK"), ("GUO", "MRT"),
+           ("GUO_LI", "MRT")]
 
 
 @pytest.mark.parametrize("prec", list(PRECISIONS))
@@ -51,8 +52,36 @@ def test_one_step_vs_bruteforce(L, scheme, coll, nx, ny, prec):
     assert err < {"f32": 2e-6, "f64": 2e-7, "mixed": 5e-7}[prec], err
 
 
+@pytest.mark.parametrize("prec", list(PRECISIONS))
+@pytest.mark.parametrize("scheme,coll", [("GUO", "BGK"), ("EDM", "BGK"), ("SC", "BGK"),
+                                         ("GUO", "MRT")])
+@pytest.mark.parametrize("eps", [0.0, 1.0])
+def test_one_step_vs_bruteforce_eq33(L, scheme, coll, eps, prec):
+    """The effective density of Eq. 33 (pressure implied by Eq. 7) on a 4 x 3 lattice."""
+    say(f"[bruteforce eq33] {scheme}-{coll} eps={eps} {prec}")
+    nx, ny, G = 4, 3, (-3.0 if eps else -4.0)
+    f = inputs.random_populations(5, nx, ny, 0.05, 1.5, 0.08).astype(np.float32)
+    wl = dict(nx=nx, ny=ny, psi_eps=eps, G=G, A=-eps / 2, scheme=scheme, collision=coll,
+              tau=0.8, s5=(1.0, 1.1, 1.2, 1.0, 1.3))
+    lat = gpu_lattice(L, wl, PRECISIONS[prec])
+    lat.set_populations(f)
+    lat.step(1)
+    g = lat.populations().astype(np.float64)
+    s5 = wl["s5"]
+    ref = BF.step(f.astype(np.float64), nx, ny, 1.0, 0.8, scheme, coll, G=G, A=-eps / 2,
+                  s=(s5[0], s5[1], s5[2], s5[3], s5[4], s5[3], s5[4], 1 / 0.8, 1 / 0.8),
+                  ss_eps=eps)
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    assert err < {"f32": 2e-6, "f64": 2e-7, "mixed": 5e-7}[prec], err
+
+
 CASES = {
     "slab_4x256_edm": workload("slab_4x256_edm"),
+    "slab_4x256_sc_tau1.3": workload("slab_4x256_edm", scheme="SC", tau=1.3),
+    "droplet_256_eq33_guo": dict(nx=256, ny=256, R=60.0, W=5.0, init="droplet", psi_eps=1.0,
+                                 G=-3.0, A=-0.5, scheme="GUO", collision="BGK", tau=1.0),
+    "droplet_256_eq33_mrt": dict(nx=256, ny=256, R=60.0, W=5.0, init="droplet", psi_eps=0.0,
+                                 G=-4.0, A=0.0, scheme="GUO", collision="MRT", tau=0.8),
     "droplet_512_li_tau0.6": workload("droplet_512_li", tau=0.6),
     "droplet_512_li_tau1.0": workload("droplet_512_li", tau=1.0),
     "droplet_512_mrt_ttc0.5": workload("droplet_4096_mrt", nx=512, ny=512, R=75.0),
@@ -75,6 +104,23 @@ def test_parity_100_steps(L, case, prec):
     say(f"    rho {e_rho:.3e}  v {e_v:.3e}")
     tol = TOL_F32 if prec == "f32" else TOL
     assert e_rho < tol and e_v < tol
+
+
+def test_sc_equals_edm_at_tau_one(L):
+    """Sec. 4.2.1: the Shan-Chen velocity shift and the exact-difference method give the same
+    result at tau = 1 (f* = f^eq(rho, u + F/rho) in both); on the GPU they agree to rounding."""
+    out = {}
+    for scheme in ("SC", "EDM"):
+        wl = workload("slab_4x256_edm", scheme=scheme, tau=1.0)
+        lat = gpu_lattice(L, wl, PRECISIONS["mixed"])
+        lat.init(initial_density(wl))
+        lat.step(200)
+        out[scheme] = lat.read()
+    d_rho = np.max(np.abs(out["SC"][0] - out["EDM"][0]) / out["EDM"][0])
+    d_v = np.max(np.abs(out["SC"][1] - out["EDM"][1])) / np.max(np.abs(out["EDM"][1]))
+    say(f"    SC vs EDM at tau = 1: rho {d_rho:.2e}  v {d_v:.2e}")
+    # two arithmetic paths with FP32 storage, each within 1e-5 of the FP64 oracle
+    assert d_rho < 1e-6 and d_v < 5e-5
 
 
 @pytest.mark.parametrize("tile", [(64, 4), (128, 2), (64, 1)])
