@@ -258,16 +258,17 @@ int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0);
 int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0);
 
 /* Warm start of lattice i from a radial profile (the learned initial state): log_rho holds 64
- * host values of log rho at r_k = 2 R k / 63, k = 0..63, r the distance from (nx/2, ny/2);
- * rho(x, y) = exp(L(r / stretch)) with L the piecewise-linear interpolant (last value held beyond
- * 2R), set at physical rest as in lbm_batch_init_rest.  mass > 0: the stretch in [1/4, 4] whose total
+ * host values of log rho at the radii r_k = r0 + k dr (k = 0..63, dr > 0), r the distance from
+ * (nx/2, ny/2); rho(x, y) = exp(L(r - shift)) with L the piecewise-linear interpolant, held at
+ * the first value below r0 and at the last beyond r0 + 63 dr; set at physical rest as in
+ * lbm_batch_init_rest.  mass > 0: the shift (within +- half the lattice diagonal) whose total
  * density sum equals `mass` (relative 1e-13; bisection) -- in a periodic box the mass fixes the
- * equilibrium, so a warm start must carry the mass of the state it replaces; mass <= 0: stretch
- * 1.  *stretch_out (may be NULL) receives the stretch.  LBM_EINVAL if a value is not finite or
- * no stretch reaches the mass; LBM_EUNSTABLE if the density leaves (0, 4/b).  Makes the lattice
- * active and resets its step count.  Synchronises. */
-int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double R, double mass,
-                           double *stretch_out);
+ * equilibrium, so a warm start must carry the mass of the state it replaces; mass <= 0: shift
+ * 0.  *shift_out (may be NULL) receives the shift.  LBM_EINVAL if a value is not finite or no
+ * shift reaches the mass; LBM_EUNSTABLE if the density leaves (0, 4/b) (Carnahan-Starling).
+ * Makes the lattice active and resets its step count.  Synchronises. */
+int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double r0, double dr,
+                           double mass, double *shift_out);
 
 /* Autotuner for the batch: times trial_steps (even) steps of every lattice for strip widths
  * tx in {64, 128, 256} with and without LBM_LAUNCH_SHALLOW, then, per size class (lattices whose

@@ -1,13 +1,13 @@
 """Oracle of the warm-start initial state (TEST INFRASTRUCTURE ONLY: called by the tests, never
 by the library or its binding).
 
-A radial profile gives log rho at r_k = 2 R k / 63, k = 0..63, r the distance from the lattice
+A radial profile gives log rho at r_k = r0 + k dr, k = 0..63, r the distance from the lattice
 centre (nx/2, ny/2).  The initial density is the piecewise-linear interpolant in r of that
-profile, stretched radially by a factor s (rho(r / s)), the last value held beyond the last
-radius, and the populations are the rest equilibria f_q = w_q rho (Eq. 2 with u = 0).  In a
-periodic box the total mass fixes the equilibrium, so the stretch is the one whose density sum
-equals the mass of the state the warm start replaces: found here by plain bisection, written
-out with numpy in FP64.
+profile, shifted radially by s (rho(r - s)), held at the first value below r0 and at the last
+beyond r0 + 63 dr, and the populations are the rest equilibria f_q = w_q rho (Eq. 2 with
+u = 0).  In a periodic box the total mass fixes the equilibrium, so the shift is the one whose
+density sum equals the mass of the state the warm start replaces: found here by plain
+bisection, written out with numpy in FP64.
 """
 from __future__ import annotations
 
@@ -17,25 +17,29 @@ POINTS = 64
 W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 
-def radii(R):
-    return 2.0 * R * np.arange(POINTS) / (POINTS - 1)
+def radii(r0, dr):
+    return r0 + dr * np.arange(POINTS)
 
 
-def density(nx, ny, R, log_profile, stretch=1.0):
+def density(nx, ny, log_profile, r0, dr, shift=0.0):
     y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
     r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2)
-    return np.exp(np.interp(r / stretch, radii(R), np.asarray(log_profile, dtype=np.float64)))
+    # np.interp holds the end values outside [r_0, r_63]
+    return np.exp(np.interp(r - shift, radii(r0, dr), np.asarray(log_profile, dtype=np.float64)))
 
 
-def populations(nx, ny, R, log_profile, stretch=1.0):
+def populations(nx, ny, log_profile, r0, dr, shift=0.0):
     """f[9][ny][nx] of the rest equilibrium of the profile density."""
-    return W[:, None, None] * density(nx, ny, R, log_profile, stretch)[None]
+    return W[:, None, None] * density(nx, ny, log_profile, r0, dr, shift)[None]
 
 
-def mass_matched_stretch(nx, ny, R, log_profile, mass, lo=0.25, hi=4.0, rtol=1e-13):
-    """The stretch in [lo, hi] whose density sum equals `mass`, or None if none does."""
+def mass_matched_shift(nx, ny, log_profile, r0, dr, mass, rtol=1e-13):
+    """The shift within +- half the lattice diagonal whose density sum equals `mass`, or None."""
+    span = 0.5 * np.hypot(nx, ny)
+    lo, hi = -span, span
+
     def excess(s):
-        return density(nx, ny, R, log_profile, s).sum() - mass
+        return density(nx, ny, log_profile, r0, dr, s).sum() - mass
     f_lo, f_hi = excess(lo), excess(hi)
     if not (f_lo < 0 < f_hi or f_hi < 0 < f_lo):
         return None

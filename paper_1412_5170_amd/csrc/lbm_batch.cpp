@@ -320,9 +320,9 @@ int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0) {
     return rc ? rc : upload_tiles(b);
 }
 
-int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double R, double mass,
-                           double *stretch_out) {
-    if (!b || i < 0 || i >= b->count || !log_rho || !(R > 0))
+int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double r0, double dr,
+                           double mass, double *shift_out) {
+    if (!b || i < 0 || i >= b->count || !log_rho || !(dr > 0) || !std::isfinite(r0))
         return bfail(b, LBM_EINVAL, "lbm_batch_init_profile: bad argument");
     for (int k = 0; k < 64; ++k)
         if (!std::isfinite(log_rho[k])) return bfail(b, LBM_EINVAL, "non-finite profile value");
@@ -335,9 +335,9 @@ int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double 
     }
     std::vector<double> host(3 * (size_t)nb);
     double lo_rho = 0, hi_rho = 0;
-    // total mass, min and max density of the profile at a stretch (partials added in order)
-    auto measure = [&](double stretch, double *sum) -> hipError_t {
-        hipError_t e = pplbm::launch_profile_mass(p, log_rho, R, stretch, part, b->stream);
+    // total mass, min and max density of the profile at a shift (partials added in order)
+    auto measure = [&](double shift, double *sum) -> hipError_t {
+        hipError_t e = pplbm::launch_profile_mass(p, log_rho, r0, dr, shift, part, b->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(double), hipMemcpyDeviceToHost,
                                b->stream);
@@ -354,46 +354,48 @@ int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double 
         hi_rho = hi;
         return hipSuccess;
     };
-    double stretch = 1.0, m = 0;
+    double shift = 0.0, m = 0;
     hipError_t e = hipSuccess;
     int rc = LBM_OK;
     if (mass > 0) {
-        // the total mass is monotone in the stretch for a profile denser inside than outside
-        // (a droplet) or the reverse (a bubble); bisection on [1/4, 4]
-        double lo = 0.25, hi = 4.0, f_lo = 0, f_hi = 0;
+        // the total mass is monotone in the shift (outwards: more of the inner phase); bisection
+        // over shifts that move the profile by up to the lattice's half diagonal
+        const double span = 0.5 * std::sqrt((double)p.nx * p.nx + (double)p.ny * p.ny);
+        double lo = -span, hi = span, f_lo = 0, f_hi = 0;
         e = measure(lo, &f_lo);
         if (e == hipSuccess) e = measure(hi, &f_hi);
         f_lo -= mass;
         f_hi -= mass;
         if (e == hipSuccess && !((f_lo < 0 && f_hi > 0) || (f_lo > 0 && f_hi < 0))) {
-            rc = bfail(b, LBM_EINVAL, "no stretch of the profile in [1/4, 4] carries that mass");
+            rc = bfail(b, LBM_EINVAL, "no shift of the profile carries that mass");
         } else {
             for (int it = 0; e == hipSuccess && it < 200; ++it) {
-                stretch = 0.5 * (lo + hi);
-                e = measure(stretch, &m);
+                shift = 0.5 * (lo + hi);
+                e = measure(shift, &m);
                 if (e != hipSuccess) break;
                 const double d = m - mass;
                 if (std::fabs(d) <= 1e-13 * mass) break;
                 if ((d < 0) == (f_lo < 0)) {
-                    lo = stretch;
+                    lo = shift;
                     f_lo = d;
                 } else {
-                    hi = stretch;
+                    hi = shift;
                 }
             }
         }
     }
-    if (e == hipSuccess && rc == LBM_OK) e = measure(stretch, &m);
+    if (e == hipSuccess && rc == LBM_OK) e = measure(shift, &m);
     if (e == hipSuccess && rc == LBM_OK && !(lo_rho > 0 && (p.psi_kind != 0 || p.b_quarter * hi_rho < 1)))
         rc = bfail(b, LBM_EUNSTABLE, "profile density outside (0, 4/b)");
-    if (e == hipSuccess && rc == LBM_OK) e = pplbm::launch_profile_init(p, log_rho, R, stretch, b->f0[i], b->stream);
+    if (e == hipSuccess && rc == LBM_OK)
+        e = pplbm::launch_profile_init(p, log_rho, r0, dr, shift, b->f0[i], b->stream);
     if (e == hipSuccess && rc == LBM_OK) e = hipStreamSynchronize(b->stream);
     (void)hipFree(part);
     if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("lbm_batch_init_profile: ") + hipGetErrorString(e));
     if (rc) return rc;
     rc = rest_state(b, i);
     if (rc) return rc;
-    if (stretch_out) *stretch_out = stretch;
+    if (shift_out) *shift_out = shift;
     b->initialised[i] = 1;
     b->active[i] = 1;
     b->steps[i] = 0;

@@ -69,10 +69,10 @@ hipError_t launch_sweep(const Physics &p, int prec, const Launch &L, const float
 // f = f^eq(rho0, u0) (Eq. 2); rho0 [ny*nx], u0 [ny*nx*2] or null, device FP64.
 // Radial-profile initial state: log_rho holds 64 values (host memory, passed by value).
 int profile_mass_blocks(const Physics &p);
-hipError_t launch_profile_mass(const Physics &p, const double *log_rho, double R, double stretch,
-                               double *partial, hipStream_t s);
-hipError_t launch_profile_init(const Physics &p, const double *log_rho, double R, double stretch,
-                               float *f, hipStream_t s);
+hipError_t launch_profile_mass(const Physics &p, const double *log_rho, double r0, double dr,
+                               double shift, double *partial, hipStream_t s);
+hipError_t launch_profile_init(const Physics &p, const double *log_rho, double r0, double dr,
+                               double shift, float *f, hipStream_t s);
 // f (holding f^eq(rho, 0)) -> f^eq(rho, -F / (2 rho)) in place; psi: a scratch psi plane.
 hipError_t launch_rest(const Physics &p, float *f, float *psi, hipStream_t s);
 hipError_t launch_init(const Physics &p, const double *rho0, const double *u0, float *f,

@@ -734,25 +734,28 @@ __global__ void __launch_bounds__(256) init_kernel(Physics p, const double *__re
     }
 }
 
-// Radial-profile initial state (warm start): rho(x, y) = exp(L(r / stretch)), r the distance
-// from the lattice centre (nx/2, ny/2), L the piecewise-linear interpolant of the 64 values
-// log rho at r_k = 2 R k / 63 (the last value held beyond 2R); f = f^eq(rho, 0).
+// Radial-profile initial state (warm start): rho(x, y) = exp(L(r - shift)), r the distance
+// from the lattice centre (nx/2, ny/2), L the piecewise-linear interpolant of 64 values of
+// log rho at r_k = r0 + k dr (k = 0..63), held at the first value below r0 and at the last
+// beyond r0 + 63 dr; f = f^eq(rho, 0).
 constexpr int kProfilePoints = 64;
 
 struct Profile {
     double v[kProfilePoints];  // log rho at r_k
-    double dr;                 // r_1 - r_0 = 2R / 63
-    double inv_stretch;
+    double r0, inv_dr;         // first radius, 1 / spacing
+    double shift;              // radial shift of the whole profile
 };
 
 __device__ __forceinline__ double profile_rho(const Profile &P, int nx, int ny, int x, int y) {
     const double dx = x - 0.5 * nx, dy = y - 0.5 * ny;
-    const double t = sqrt(dx * dx + dy * dy) * P.inv_stretch / P.dr;
-    int k = (int)t;
+    const double t = (sqrt(dx * dx + dy * dy) - P.shift - P.r0) * P.inv_dr;
     double l;
-    if (k >= kProfilePoints - 1) {
+    if (!(t > 0)) {
+        l = P.v[0];
+    } else if (t >= kProfilePoints - 1) {
         l = P.v[kProfilePoints - 1];
     } else {
+        const int k = (int)t;
         const double w = t - k;
         l = P.v[k] + w * (P.v[k + 1] - P.v[k]);
     }
@@ -1166,11 +1169,12 @@ hipError_t launch_macro(const Physics &p, const float *f, const float *psi, doub
 }
 
 namespace {
-Profile make_profile(const double *log_rho, double R, double stretch) {
+Profile make_profile(const double *log_rho, double r0, double dr, double shift) {
     Profile P;
     for (int k = 0; k < kProfilePoints; ++k) P.v[k] = log_rho[k];
-    P.dr = 2.0 * R / (kProfilePoints - 1);
-    P.inv_stretch = 1.0 / stretch;
+    P.r0 = r0;
+    P.inv_dr = 1.0 / dr;
+    P.shift = shift;
     return P;
 }
 }  // namespace
@@ -1180,17 +1184,17 @@ int profile_mass_blocks(const Physics &p) {
     return (int)(b < 1024 ? b : 1024);
 }
 
-hipError_t launch_profile_mass(const Physics &p, const double *log_rho, double R, double stretch,
-                               double *partial, hipStream_t s) {
+hipError_t launch_profile_mass(const Physics &p, const double *log_rho, double r0, double dr,
+                               double shift, double *partial, hipStream_t s) {
     hipLaunchKernelGGL(profile_mass_kernel, dim3(profile_mass_blocks(p)), dim3(256), 0, s, p.nx,
-                       p.ny, make_profile(log_rho, R, stretch), partial);
+                       p.ny, make_profile(log_rho, r0, dr, shift), partial);
     return hipGetLastError();
 }
 
-hipError_t launch_profile_init(const Physics &p, const double *log_rho, double R, double stretch,
-                               float *f, hipStream_t s) {
+hipError_t launch_profile_init(const Physics &p, const double *log_rho, double r0, double dr,
+                               double shift, float *f, hipStream_t s) {
     hipLaunchKernelGGL(profile_init_kernel, row_grid(p.nx, p.ny, 256), dim3(256), 0, s, p,
-                       make_profile(log_rho, R, stretch), f);
+                       make_profile(log_rho, r0, dr, shift), f);
     return hipGetLastError();
 }
 

@@ -293,7 +293,7 @@ _BSIG = {
     "lbm_batch_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int, _D]),
     "lbm_batch_init_rest": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "lbm_batch_init_profile": (ctypes.c_int, [_P, ctypes.c_int, _D, ctypes.c_double,
-                                              ctypes.c_double, _D]),
+                                              ctypes.c_double, ctypes.c_double, _D]),
     "lbm_batch_set_active": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_batch_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
@@ -366,15 +366,15 @@ class Batch:
         assert rho0.shape == (m["ny"], m["nx"])
         bcheck(lbm_batch_init_rest(self.b, i, _dptr(rho0)), self.b)
 
-    def init_profile(self, i, log_rho, R, mass=0.0):
-        """Warm start from 64 values of log rho at r_k = 2 R k / 63; with mass > 0 the profile
-        is stretched radially to carry exactly that total mass.  Returns the stretch."""
+    def init_profile(self, i, log_rho, r0, dr, mass=0.0):
+        """Warm start from 64 values of log rho at r_k = r0 + k dr; with mass > 0 the profile is
+        shifted radially to carry exactly that total mass.  Returns the shift."""
         log_rho = np.ascontiguousarray(log_rho, dtype=np.float64)
         assert log_rho.shape == (64,)
-        stretch = ctypes.c_double(0.0)
-        bcheck(lbm_batch_init_profile(self.b, i, _dptr(log_rho), float(R), float(mass),
-                                      ctypes.byref(stretch)), self.b)
-        return stretch.value
+        shift = ctypes.c_double(0.0)
+        bcheck(lbm_batch_init_profile(self.b, i, _dptr(log_rho), float(r0), float(dr),
+                                      float(mass), ctypes.byref(shift)), self.b)
+        return shift.value
 
     def autotune(self, cache_path=None, trial_steps=20):
         """Pick strip width, prefetch depth and segment heights per size class by timed trials

@@ -2,13 +2,14 @@
 
 A small network (4 -> 128 -> 128 -> 128 -> 64, tanh, FP32, the library's own GPU forward,
 backward and Adam kernels) maps a droplet's (T/Tc, tau, R, K) to its equilibrium radial density
-profile (log rho at r_k = 2 R k / 63, k = 0..63).  It is trained on equilibria that the batched
-sweep itself produces from plain tanh initial states; at run time its profile, expanded on the device
-and stretched radially so that its total mass equals that of the tanh state it replaces (in a
-periodic box the mass fixes the equilibrium), initialises the lattice (f = f^eq(rho0, 0)), with
-the tanh state as the fallback when a prediction is not a valid density.  Both runs stop on the same tolerances (velocity change and probe-density change
-per step); a much longer run from the tanh state gives the converged density ratio that the two are
-measured against.
+profile: log rho at 64 radii centred on the initial radius, r_k = R + 1.5 (k - 31.5).  It is
+trained on equilibria that the batched sweep itself produces from plain tanh initial states.
+At run time its profile is expanded on the device, shifted radially so that its total mass
+equals that of the tanh state it replaces (in a periodic box the mass fixes the equilibrium),
+and set at physical rest (f = f^eq(rho, -F/(2 rho))); the tanh state is the fallback when a
+prediction is not a valid density.  Both runs stop on the same tolerances (velocity change and
+probe-density change per step); a longer, tighter run from the tanh state gives the converged
+density ratio that the two are measured against.
 
     python -m paper_1412_5170_amd.warmstart --out results.json
 """
@@ -33,10 +34,11 @@ def say(*a):
 
 
 def features(m):
-    """(T/Tc, tau, R, K) scaled to about [-1, 1] (R and K on a log scale)."""
+    """(T/Tc, tau, R, K) scaled to about [-1, 1]: R through the curvature (48/R - 1, which
+    stays bounded for large droplets), K on a log scale."""
     return np.array([(m["T_over_Tc"] - 0.7) / 0.2,
                      (m["tau"] - 1.05) / 0.45,
-                     (math.log(m["R"]) - math.log(48.0)) / math.log(2.0),
+                     48.0 / m["R"] - 1.0,
                      (math.log(m["K"]) - 0.5 * math.log(K_RANGE[0] * K_RANGE[1]))
                      / (0.5 * math.log(K_RANGE[1] / K_RANGE[0]))], dtype=np.float32)
 
@@ -114,22 +116,22 @@ class Surrogate:
         return y.cpu().numpy() * self.std + self.mean
 
     def warm_start(self, lbm, m):
-        """The learned initial state of member m: its predicted profile, to be stretched on the
+        """The learned initial state of member m: its predicted profile, to be shifted on the
         device to the mass of the tanh state it replaces (in a periodic box the mass fixes the
         equilibrium), with that tanh state as the fallback."""
         plain = sweep.tanh_density(lbm, m)
         prof = self.predict_log(features(m)[None])[0]
         if not np.all(np.isfinite(prof)):
             return plain
-        return sweep.WarmStart(prof, plain.sum(), plain)
+        return sweep.WarmStart(prof, m["R"], plain.sum(), plain)
 
 
-def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho=0.0,
-             reference=True):
-    """Plain (tanh) and warm-started runs of the same members; wall time, steps and the
-    density ratio each reaches.  With `reference`, a third, untimed run from the tanh state for
-    a fixed 4x the plain run's longest step count (at least 100 000 steps) gives the converged
-    ratio that both are measured against."""
+def evaluate(lbm, sur, members, tol, tol_rho, check_every=500, max_steps=1_500_000,
+             chunk=20_000, reference=True):
+    """Plain (tanh) and warm-started runs of the same members from physical rest, same
+    tolerances; wall time, lattice updates and the density ratio each reaches.  With
+    `reference`, a third, untimed run from the tanh state with both tolerances 4x tighter over
+    4x longer check windows gives the converged ratio that both are measured against."""
     res = {}
     modes = ("tanh", "learned") + (("reference",) if reference else ())
     for mode in modes:
@@ -138,37 +140,31 @@ def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho
         else:
             inits = [sweep.tanh_density(lbm, m) for m in members]
         fallback = sum(not isinstance(x, sweep.WarmStart) for x in inits) if mode == "learned" else 0
-        if mode == "reference":  # no convergence test: every member runs ref_steps
-            ref_steps = max(4 * max(res["tanh"]["steps"]), 100_000)
-            ref_steps += -ref_steps % check_every
-            run = dict(tol=1e-300, tol_rho=0.0, max_steps=ref_steps)
-        else:
-            run = dict(tol=tol, tol_rho=tol_rho, max_steps=max_steps)
-        wall, steps, status, b = sweep.run_batch(lbm, members, inits, check_every=check_every,
-                                                 **run)
+        k = 4 if mode == "reference" else 1
+        wall, steps, status, b = sweep.run_batch(
+            lbm, members, inits, tol=tol / k, tol_rho=tol_rho / k, check_every=check_every * k,
+            max_steps=max_steps, chunk=chunk, report=lambda t: say(f"warmstart {mode}: {t}"))
         fallback += b.fallbacks
         ratios = []
         for i, m in enumerate(members):
             rho, _ = b.read(i)
             ratios.append(float(rho[m["ny"] // 2, m["nx"] // 2] / rho[0, 0]))
         del b
-        lu = sum(m["nx"] * m["ny"] * s for m, s in zip(members, steps))
-        res[mode] = {"wall_s": round(wall, 3), "steps": [int(s) for s in steps],
-                     "status": [int(s) for s in status], "ratio": ratios,
+        lu = sum(m["nx"] * m["ny"] * st for m, st in zip(members, steps))
+        res[mode] = {"wall_s": round(wall, 3), "steps": [int(x) for x in steps],
+                     "status": [int(x) for x in status], "ratio": ratios,
                      "lattice_updates": int(lu), "fallbacks": fallback}
-        say(f"warmstart: {mode}: {wall:.2f} s, {lu / 1e9:.2f} G lattice updates, "
-            f"max steps {max(steps)}, not converged {sum(int(s != 0) for s in status)}")
+        say(f"warmstart: {mode}: {wall:.2f} s, {lu / 1e9:.1f} G lattice updates, "
+            f"max steps {max(steps)}, not converged {sum(int(x != 0) for x in status)}")
     rt, rl = np.array(res["tanh"]["ratio"]), np.array(res["learned"]["ratio"])
     res["ratio_rel_diff_max"] = float(np.max(np.abs(rl - rt) / rt))
     if reference:
         rr = np.array(res["reference"]["ratio"])
-        res["ratio_err_tanh_max"] = float(np.max(np.abs(rt - rr) / rr))
-        res["ratio_err_learned_max"] = float(np.max(np.abs(rl - rr) / rr))
-        for i, m in enumerate(members):
-            say(f"warmstart: member {i} n={m['nx']} T/Tc={m['T_over_Tc']:.3f} tau={m['tau']:.3f} "
-                f"{m['collision']}: steps {res['tanh']['steps'][i]} -> "
-                f"{res['learned']['steps'][i]}, ratio {rt[i]:.6g} / {rl[i]:.6g} "
-                f"(reference {rr[i]:.6g})")
+        et, el = np.abs(rt - rr) / rr, np.abs(rl - rr) / rr
+        res["ratio_err_tanh_max"] = float(et.max())
+        res["ratio_err_learned_max"] = float(el.max())
+        res["ratio_err_tanh_median"] = float(np.median(et))
+        res["ratio_err_learned_median"] = float(np.median(el))
     res["speedup_wall"] = res["tanh"]["wall_s"] / res["learned"]["wall_s"]
     res["speedup_updates"] = res["tanh"]["lattice_updates"] / res["learned"]["lattice_updates"]
     return res
@@ -176,56 +172,73 @@ def evaluate(lbm, sur, members, tol, check_every=500, max_steps=400_000, tol_rho
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-count", type=int, default=1024)
+    ap.add_argument("--train-count", type=int, default=2000)
     ap.add_argument("--train-tol", type=float, default=1e-8)
+    ap.add_argument("--train-tol-rho", type=float, default=1e-8)
     ap.add_argument("--train-levels", type=int, default=19, help="sizes 96 + 16 k, k < levels")
-    ap.add_argument("--eval-count", type=int, default=32)
-    ap.add_argument("--eval-levels", type=int, default=17, help="sizes 128 + 16 k, k < levels")
+    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--eval-seed", type=int, default=0)
+    ap.add_argument("--eval-count", type=int, default=64)
+    ap.add_argument("--eval-levels", type=int, default=57, help="sizes 128 + 16 k, k < levels")
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--tol-rho", type=float, default=2e-9,
                     help="per-step relative change of the probe densities at convergence")
-    ap.add_argument("--train-tol-rho", type=float, default=1e-8)
-    ap.add_argument("--train-steps", type=int, default=6000)
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--data", default=None, help="npz of (X, Y) to reuse instead of generating")
+    ap.add_argument("--save-net", default=None, help="npz to write the trained network to")
+    ap.add_argument("--load-net", default=None, help="npz of a trained network (skip training)")
+    ap.add_argument("--no-eval", action="store_true")
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from . import lbm
 
     out = {"dims": DIMS}
-    if a.data:
-        d = np.load(a.data)
-        X, Y = d["X"], d["Y"]
-    else:
-        tr = draw_training(1, a.train_count, n_levels=a.train_levels)
-        t0 = time.perf_counter()
-        prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
-        ok = status == 0
-        X = np.stack([features(m) for m in tr])[ok]
-        Y = prof[ok]
-        out["generation"] = {"members": len(tr), "converged": int(ok.sum()),
-                             "wall_s": round(time.perf_counter() - t0, 1), "tol": a.train_tol,
-                             "lattice_updates": int(sum(m["nx"] * m["ny"] * s
-                                                        for m, s in zip(tr, steps)))}
-        if a.out:
-            np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
     sur = Surrogate(lbm, seed=0)
-    t0 = time.perf_counter()
-    out["training"] = sur.fit(X, Y, steps=a.train_steps)
-    out["training"]["wall_s"] = round(time.perf_counter() - t0, 1)
-    ev = sweep.members_from_draw(inputs.batch_draw(0, count=a.eval_count, n_levels=a.eval_levels))
-    out["evaluation"] = evaluate(lbm, sur, ev, a.tol, tol_rho=a.tol_rho)
-    out["evaluation"]["members"] = [{k: m[k] for k in ("nx", "T_over_Tc", "tau", "collision")}
-                                    for m in ev]
-    line = json.dumps(out)
+    if a.load_net:
+        d = np.load(a.load_net)
+        sur.net.set_params(d["params"])
+        sur.mean, sur.std = d["mean"], d["std"]
+        out["training"] = {"loaded": a.load_net}
+    else:
+        if a.data:
+            d = np.load(a.data)
+            X, Y = d["X"], d["Y"]
+        else:
+            tr = draw_training(1, a.train_count, n_levels=a.train_levels)
+            t0 = time.perf_counter()
+            prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
+            ok = status == 0
+            X = np.stack([features(m) for m in tr])[ok]
+            Y = prof[ok]
+            out["generation"] = {"members": len(tr), "converged": int(ok.sum()),
+                                 "wall_s": round(time.perf_counter() - t0, 1),
+                                 "tol": a.train_tol, "lattice_updates": int(sum(
+                                     m["nx"] * m["ny"] * st for m, st in zip(tr, steps)))}
+            if a.out:
+                np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
+        t0 = time.perf_counter()
+        out["training"] = sur.fit(X, Y, steps=a.train_steps)
+        out["training"]["wall_s"] = round(time.perf_counter() - t0, 1)
+        if a.save_net:
+            np.savez(a.save_net, params=sur.net.get_params(), mean=sur.mean, std=sur.std)
+    say(json.dumps(out))
+    if not a.no_eval:
+        ev = sweep.members_from_draw(inputs.batch_draw(a.eval_seed, count=a.eval_count,
+                                                       n_levels=a.eval_levels))
+        out["evaluation"] = evaluate(lbm, sur, ev, a.tol, a.tol_rho,
+                                     reference=not a.no_reference)
+        out["evaluation"]["members"] = [{k: m[k] for k in ("nx", "T_over_Tc", "tau", "collision")}
+                                        for m in ev]
+        e = out["evaluation"]
+        say(json.dumps({k: e[k] for k in ("speedup_wall", "speedup_updates",
+                                          "ratio_rel_diff_max", "ratio_err_tanh_max",
+                                          "ratio_err_learned_max", "ratio_err_tanh_median",
+                                          "ratio_err_learned_median") if k in e}
+                       | {"tanh_wall_s": e["tanh"]["wall_s"],
+                          "learned_wall_s": e["learned"]["wall_s"]}))
     if a.out:
         with open(a.out, "w") as fh:
-            fh.write(line + "\n")
-    say(json.dumps({k: out[k] for k in out if k != "evaluation"}))
-    e = out["evaluation"]
-    say(json.dumps({k: e[k] for k in ("speedup_wall", "speedup_updates", "ratio_rel_diff_max",
-                                      "ratio_err_tanh_max", "ratio_err_learned_max") if k in e}
-                   | {"tanh_wall_s": e["tanh"]["wall_s"],
-                      "learned_wall_s": e["learned"]["wall_s"]}))
+            json.dump(out, fh)
 
 
 if __name__ == "__main__":

@@ -35,26 +35,30 @@ def _oracle_params(m):
                          K=m["K"], scheme=oracle.GUO_LI, sigma=m["sigma"], tau=m["tau"])
 
 
+H = 1.5  # profile spacing
+
+
 def _profile(R, inner=0.35, outer=0.02, width=4.0):
-    r = oprof.radii(R)
+    r = R + H * (np.arange(64) - 31.5)
     return np.log(outer + (inner - outer) * 0.5 * (1 - np.tanh((r - R) / width)))
 
 
-@pytest.mark.parametrize("nx,ny,R,stretch", [(130, 96, 20.0, 1.0), (64, 200, 12.5, 1.37),
-                                             (5, 3, 1.0, 1.0)])
-def test_profile_init_matches_oracle(L, nx, ny, R, stretch):
-    say(f"profile init {nx}x{ny} R={R} stretch={stretch}")
+@pytest.mark.parametrize("nx,ny,R,shift", [(130, 96, 30.0, 0.0), (64, 200, 20.0, 3.7),
+                                           (5, 3, 1.0, 0.0)])
+def test_profile_init_matches_oracle(L, nx, ny, R, shift):
+    say(f"profile init {nx}x{ny} R={R} shift={shift}")
     m = _member(nx, ny)
     prof = _profile(R)
+    r0 = R - 31.5 * H
     b = L.Batch([m])
-    mass = oprof.density(nx, ny, R, prof, stretch).sum() if stretch != 1.0 else 0.0
-    s = b.init_profile(0, prof, R, mass)
-    if stretch == 1.0:
-        assert s == 1.0
+    mass = oprof.density(nx, ny, prof, r0, H, shift).sum() if shift else 0.0
+    s = b.init_profile(0, prof, r0, H, mass)
+    if not shift:
+        assert s == 0.0
     else:
-        assert abs(s - stretch) < 1e-9
+        assert abs(s - shift) < 1e-9
     f = b.populations(0).astype(np.float64)
-    rho_ref = oprof.density(nx, ny, R, prof, s)
+    rho_ref = oprof.density(nx, ny, prof, r0, H, s)
     ref = oprof.rest_populations(_oracle_params(m), rho_ref)
     # FP32 storage, and a force from the FP32-rounded rest populations
     assert np.max(np.abs(f - ref) / ref) < 1e-6
@@ -71,18 +75,22 @@ def test_profile_init_errors(L):
     b = L.Batch([_member(64, 64)])
     flat = np.log(np.full(64, 0.1))
     with pytest.raises(L.LBMError) as e:
-        b.init_profile(0, flat, 16.0, 2 * 0.1 * 64 * 64)  # no stretch changes a uniform mass
+        b.init_profile(0, flat, 0.0, H, 2 * 0.1 * 64 * 64)  # no shift changes a uniform mass
     assert e.value.code == L.LBM_EINVAL
     bad = _profile(16.0)
     bad[5] = np.nan
     with pytest.raises(L.LBMError) as e:
-        b.init_profile(0, bad, 16.0)
+        b.init_profile(0, bad, 0.0, H)
     assert e.value.code == L.LBM_EINVAL
     dense = np.log(np.full(64, 1.2))  # above the packing limit 4/b = 1
     with pytest.raises(L.LBMError) as e:
-        b.init_profile(0, dense, 16.0)
+        b.init_profile(0, dense, 0.0, H)
     assert e.value.code == L.LBM_EUNSTABLE
+    with pytest.raises(L.LBMError) as e:
+        b.init_profile(0, _profile(16.0), 0.0, 0.0)  # spacing must be positive
+    assert e.value.code == L.LBM_EINVAL
     assert b.stats()[0]["step"] == 0  # a rejected profile leaves the lattice uninitialised
+
 
 def test_rest_state_matches_oracle(L):
     m = _member(96, 80)
@@ -100,7 +108,7 @@ def test_rest_state_matches_oracle(L):
 def test_warm_start_gain(L):
     """From the droplet's own equilibrium density at physical rest: at most half the steps of
     the tanh start, same density ratio.  From the mass-matched radial profile of that
-    equilibrium (64 samples along +x): fewer steps, same ratio."""
+    equilibrium (64 samples along +x, centred on the interface): fewer steps, same ratio."""
     from paper_1412_5170_amd import sweep
     m = dict(sweep.PHYSICS, nx=128, ny=128, T_over_Tc=0.7, tau=1.0, collision="BGK", R=32.0)
     plain = sweep.tanh_density(L, m)
@@ -113,7 +121,8 @@ def test_warm_start_gain(L):
     rho1, _ = b1.read(0)
     ratio1 = rho1[64, 64] / rho1[0, 0]
     prof = sweep.radial_profile(m, rho0)
-    w2, s2, st2, b2 = sweep.run_batch(L, [m], [sweep.WarmStart(prof, plain.sum(), plain)], **run)
+    w2, s2, st2, b2 = sweep.run_batch(L, [m], [sweep.WarmStart(prof, m["R"], plain.sum(), plain)],
+                                      **run)
     rho2, _ = b2.read(0)
     ratio2 = rho2[64, 64] / rho2[0, 0]
     say(f"warm start gain: steps tanh {s0[0]}, exact rest {s1[0]}, profile {s2[0]}; "

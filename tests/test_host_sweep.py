@@ -3,6 +3,7 @@ warm-start initial state (radial profile to lattice, mass matching) pinned to ge
 import math
 
 import numpy as np
+import pytest
 
 from oracle import profile as oprof
 from paper_1412_5170_amd import inputs, sweep, warmstart
@@ -12,17 +13,20 @@ def _member(n=160, R=40.0):
     return dict(sweep.PHYSICS, nx=n, ny=n, R=R, T_over_Tc=0.6, tau=1.0, collision="BGK")
 
 
-def test_profile_radii_agree():
-    assert np.array_equal(sweep.profile_radii(37.5), oprof.radii(37.5))
-    assert sweep.PROFILE_POINTS == oprof.POINTS == 64
+def test_profile_radii_are_centred_on_the_interface():
+    r = sweep.profile_radii(40.0)
+    assert len(r) == sweep.PROFILE_POINTS == oprof.POINTS == 64
+    assert np.allclose(np.diff(r), sweep.PROFILE_SPACING)
+    assert (r[31] + r[32]) / 2 == pytest.approx(40.0)
+    assert np.array_equal(r, oprof.radii(r[0], sweep.PROFILE_SPACING))
 
 
 def test_profile_round_trip():
     """A smooth radial profile expanded to the lattice and sampled back along +x is itself."""
     m = _member()
     r = sweep.profile_radii(m["R"])
-    prof = np.log(0.2 + 0.19 * np.tanh((30.0 - r) / 6.0))
-    rho = oprof.density(m["nx"], m["ny"], m["R"], prof)
+    prof = np.log(0.2 + 0.19 * np.tanh((38.0 - r) / 6.0))
+    rho = oprof.density(m["nx"], m["ny"], prof, r[0], sweep.PROFILE_SPACING)
     back = sweep.radial_profile(m, rho)
     # two linear interpolations (profile to lattice, lattice to profile) of a steep log profile
     assert np.max(np.abs(back - prof)) < 2e-2
@@ -31,8 +35,8 @@ def test_profile_round_trip():
 
 def test_profile_is_rest_equilibrium():
     prof = np.log(np.linspace(0.3, 0.01, 64))
-    f = oprof.populations(40, 30, 10.0, prof)
-    rho = oprof.density(40, 30, 10.0, prof)
+    f = oprof.populations(40, 30, prof, 2.0, 0.25)
+    rho = oprof.density(40, 30, prof, 2.0, 0.25)
     assert np.allclose(f.sum(axis=0), rho, rtol=1e-15)
     ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
     ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
@@ -40,48 +44,46 @@ def test_profile_is_rest_equilibrium():
     assert np.abs(np.tensordot(ey, f, 1)).max() < 1e-17
 
 
-def test_profile_centre_and_far_field():
-    """The centre node takes the first value, nodes beyond 2R s take the last."""
+def test_profile_ends_are_held():
+    """Nodes inside the first radius take the first value, nodes beyond the last the last."""
     prof = np.log(np.linspace(0.4, 0.02, 64))
-    rho = oprof.density(64, 64, 8.0, prof, stretch=1.5)
+    rho = oprof.density(64, 64, prof, 5.0, 0.25, shift=2.0)   # radii 7 .. 22.75 after the shift
     assert math.isclose(rho[32, 32], 0.4, rel_tol=1e-15)
-    assert math.isclose(rho[0, 0], 0.02, rel_tol=1e-15)  # r = 45 > 2 R s = 24
+    assert math.isclose(rho[0, 0], 0.02, rel_tol=1e-15)
 
 
 def test_mass_match_disk_closed_form():
     """A sharp disk (rho_l inside radius a, rho_g outside) holds about
-    rho_g N + (rho_l - rho_g) pi (a s)^2: the matched stretch follows that area law."""
-    n, R = 256, 40.0
-    r = oprof.radii(R)
-    a = 30.0
+    rho_g N + (rho_l - rho_g) pi a^2: the matched shift follows that area law."""
+    n = 256
+    r = sweep.profile_radii(60.0)
     rl, rg = 0.4, 0.01
-    # a steep but resolved edge between profile radii (the profile is linear between them)
-    prof = np.log(np.where(r < a, rl, rg))
-    for s_true in (0.8, 1.0, 1.3):
-        area = math.pi * (a * s_true) ** 2
-        mass = rg * n * n + (rl - rg) * area
-        s = oprof.mass_matched_stretch(n, n, R, prof, mass)
+    prof = np.log(np.where(r < 60.0, rl, rg))
+    for a in (50.0, 60.0, 75.0):
+        mass = rg * n * n + (rl - rg) * math.pi * a * a
+        s = oprof.mass_matched_shift(n, n, prof, r[0], sweep.PROFILE_SPACING, mass)
         assert s is not None
-        assert abs(s - s_true) / s_true < 0.02  # lattice count of a disk vs its area
+        assert abs((60.0 + s) - a) < 0.6  # lattice count of a disk vs its area, step width
 
 
 def test_mass_match_is_exact_and_monotone():
     m = _member()
     r = sweep.profile_radii(m["R"])
-    prof = np.log(0.2 + 0.19 * np.tanh((35.0 - r) / 4.0))
-    base = oprof.density(m["nx"], m["ny"], m["R"], prof).sum()
+    h = sweep.PROFILE_SPACING
+    prof = np.log(0.2 + 0.19 * np.tanh((40.0 - r) / 4.0))
+    d = lambda s: oprof.density(m["nx"], m["ny"], prof, r[0], h, s).sum()
+    base = d(0.0)
     for target in (0.9 * base, base, 1.2 * base):
-        s = oprof.mass_matched_stretch(m["nx"], m["ny"], m["R"], prof, target)
+        s = oprof.mass_matched_shift(m["nx"], m["ny"], prof, r[0], h, target)
         assert s is not None
-        assert abs(oprof.density(m["nx"], m["ny"], m["R"], prof, s).sum() - target) <= 1e-12 * target
-    # stretching a droplet (dense inside) raises its mass
-    d = lambda s: oprof.density(m["nx"], m["ny"], m["R"], prof, s).sum()
-    assert d(1.1) > base > d(0.9)
+        assert abs(d(s) - target) <= 1e-12 * target
+    # moving a droplet's interface outwards (dense inside) raises its mass
+    assert d(2.0) > base > d(-2.0)
 
 
 def test_mass_match_unreachable_is_none():
-    prof = np.log(np.full(64, 0.1))  # uniform: no stretch changes the mass
-    assert oprof.mass_matched_stretch(160, 160, 40.0, prof, 2.0 * 0.1 * 160 * 160) is None
+    prof = np.log(np.full(64, 0.1))  # uniform: no shift changes the mass
+    assert oprof.mass_matched_shift(160, 160, prof, 10.0, 1.5, 2.0 * 0.1 * 160 * 160) is None
 
 
 def test_features_span_unit_box():
@@ -89,6 +91,9 @@ def test_features_span_unit_box():
     X = np.stack([warmstart.features(m) for m in ms])
     assert X.shape == (256, 4) and X.dtype == np.float32
     assert np.all(np.abs(X) <= 1.0 + 1e-6)
+    # the curvature feature stays bounded for the largest droplets of the sweep
+    big = dict(ms[0], R=256.0)
+    assert -1.0 <= warmstart.features(big)[2] <= 0.0
     assert all(warmstart.K_RANGE[0] <= m["K"] <= warmstart.K_RANGE[1] for m in ms)
 
 
