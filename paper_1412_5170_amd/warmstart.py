@@ -126,6 +126,123 @@ class Surrogate:
         return sweep.WarmStart(prof, m["R"], plain.sum(), plain)
 
 
+def _start(lbm, sur, members, mode):
+    if mode == "learned":
+        return [sur.warm_start(lbm, m) for m in members]
+    return [sweep.tanh_density(lbm, m) for m in members]
+
+
+def _batch(lbm, members, inits):
+    b = lbm.Batch(members)
+    fallback = 0
+    for i, init in enumerate(inits):
+        if isinstance(init, sweep.WarmStart):
+            try:
+                b.init_profile(i, init.log_profile, init.r0, init.dr, init.mass)
+                continue
+            except lbm.LBMError:
+                fallback += 1
+                init = init.fallback
+        b.init_rest(i, init)
+    b.sync()
+    return b, fallback
+
+
+def trajectories(lbm, members, inits, tol, tol_rho, check_every, max_steps, label):
+    """Run every member until it meets the stopping rule (as lbm_batch_run: velocity change and
+    probe-density change per step below tol, tol_rho), recording the probe density ratio at
+    every check.  Returns per-member lists of (step, ratio) and the final ratios."""
+    b, _ = _batch(lbm, members, inits)
+    n = len(members)
+    hist = [[] for _ in range(n)]
+    prev = b.stats(track_dv=True)
+    active = [True] * n
+    t0, last = time.perf_counter(), time.perf_counter()
+    while any(active):
+        b.step(check_every)
+        st = b.stats(track_dv=True)
+        for i in range(n):
+            if not active[i]:
+                continue
+            a, c = st[i]["rho_probe_a"], st[i]["rho_probe_b"]
+            hist[i].append((st[i]["step"], a / c))
+            dr = max(abs(a - prev[i]["rho_probe_a"]) / a,
+                     abs(c - prev[i]["rho_probe_b"]) / c) / check_every
+            done = st[i]["nonfinite"] or (st[i]["dv_max"] / check_every < tol and dr < tol_rho)
+            if done or st[i]["step"] >= max_steps:
+                active[i] = False
+                b.set_active(i, 0)
+        prev = st
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            say(f"warmstart {label}: {sum(active)} running, step {max(h[-1][0] for h in hist)}, "
+                f"{last - t0:.0f} s")
+    del b
+    return hist, [h[-1][1] for h in hist]
+
+
+def time_to_accuracy(hist, ref, eps):
+    """First recorded step from which |ratio - ref| / ref stays below eps to the end."""
+    for k in range(len(hist)):
+        if all(abs(r - ref) / ref < eps for _, r in hist[k:]):
+            return hist[k][0]
+    return hist[-1][0]
+
+
+def budgeted(lbm, members, inits, budgets, check_every, label):
+    """Timed run in which member i stops after budgets[i] steps (a multiple of check_every)."""
+    b, fallback = _batch(lbm, members, inits)
+    n = len(members)
+    active = [True] * n
+    steps = 0
+    t0 = time.perf_counter()
+    while any(active):
+        b.step(check_every)
+        steps += check_every
+        for i in range(n):
+            if active[i] and steps >= budgets[i]:
+                active[i] = False
+                b.set_active(i, 0)
+    b.sync()
+    wall = time.perf_counter() - t0
+    ratios = []
+    for i, m in enumerate(members):
+        rho, _ = b.read(i)
+        ratios.append(float(rho[m["ny"] // 2, m["nx"] // 2] / rho[0, 0]))
+    del b
+    lu = sum(m["nx"] * m["ny"] * bb for m, bb in zip(members, budgets))
+    say(f"warmstart {label}: budgeted run {wall:.1f} s, {lu / 1e9:.0f} G lattice updates")
+    return wall, lu, ratios, fallback
+
+
+def equal_accuracy(lbm, sur, members, eps=1e-4, tol=2.5e-10, tol_rho=5e-10, check_every=500,
+                   max_steps=1_500_000):
+    """Wall time to the same density-ratio accuracy: trajectories from both starts under a
+    stopping rule 4x tighter than the sweep's give the converged ratio (their mean; their
+    difference bounds its uncertainty) and, per member and start, the first step from which the
+    ratio stays within eps of it; then each start runs timed with exactly those per-member
+    step budgets."""
+    res = {"eps": eps}
+    hist, fin = {}, {}
+    for mode in ("tanh", "learned"):
+        hist[mode], fin[mode] = trajectories(lbm, members, _start(lbm, sur, members, mode), tol,
+                                             tol_rho, check_every, max_steps, mode)
+    ref = [(a + b) / 2 for a, b in zip(fin["tanh"], fin["learned"])]
+    res["reference_spread_max"] = float(max(abs(a - b) / r for a, b, r in
+                                            zip(fin["tanh"], fin["learned"], ref)))
+    for mode in ("tanh", "learned"):
+        budgets = [time_to_accuracy(h, r, eps) for h, r in zip(hist[mode], ref)]
+        wall, lu, ratios, fb = budgeted(lbm, members, _start(lbm, sur, members, mode), budgets,
+                                        check_every, mode)
+        err = [abs(x - r) / r for x, r in zip(ratios, ref)]
+        res[mode] = {"wall_s": round(wall, 3), "lattice_updates": int(lu),
+                     "steps": [int(x) for x in budgets], "ratio_err_max": float(max(err)),
+                     "ratio_err_median": float(np.median(err)), "fallbacks": fb}
+    res["speedup_wall"] = res["tanh"]["wall_s"] / res["learned"]["wall_s"]
+    res["speedup_updates"] = res["tanh"]["lattice_updates"] / res["learned"]["lattice_updates"]
+    return res
+
+
 def evaluate(lbm, sur, members, tol, tol_rho, check_every=500, max_steps=1_500_000,
              chunk=20_000, reference=True):
     """Plain (tanh) and warm-started runs of the same members from physical rest, same
@@ -188,6 +305,8 @@ def main(argv=None):
     ap.add_argument("--save-net", default=None, help="npz to write the trained network to")
     ap.add_argument("--load-net", default=None, help="npz of a trained network (skip training)")
     ap.add_argument("--no-eval", action="store_true")
+    ap.add_argument("--equal-accuracy", action="store_true",
+                    help="time both starts to the same density-ratio accuracy (eps 1e-4)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from . import lbm
@@ -222,7 +341,17 @@ def main(argv=None):
         if a.save_net:
             np.savez(a.save_net, params=sur.net.get_params(), mean=sur.mean, std=sur.std)
     say(json.dumps(out))
-    if not a.no_eval:
+    if a.equal_accuracy:
+        ev = sweep.members_from_draw(inputs.batch_draw(a.eval_seed, count=a.eval_count,
+                                                       n_levels=a.eval_levels))
+        out["equal_accuracy"] = equal_accuracy(lbm, sur, ev)
+        e = out["equal_accuracy"]
+        say(json.dumps({k: e[k] for k in ("eps", "reference_spread_max", "speedup_wall",
+                                          "speedup_updates")}
+                       | {m: {k: e[m][k] for k in ("wall_s", "lattice_updates", "ratio_err_max",
+                                                   "ratio_err_median")}
+                          for m in ("tanh", "learned")}))
+    elif not a.no_eval:
         ev = sweep.members_from_draw(inputs.batch_draw(a.eval_seed, count=a.eval_count,
                                                        n_levels=a.eval_levels))
         out["evaluation"] = evaluate(lbm, sur, ev, a.tol, a.tol_rho,

@@ -123,3 +123,10 @@ def test_rest_populations_have_zero_fluid_velocity():
     F = np.hypot(fl["Fx"], fl["Fy"]) / (2 * rho)
     assert F.max() > 1e-4
     assert np.abs(fl["vx"]).max() < 1e-15 and np.abs(fl["vy"]).max() < 1e-15
+
+
+def test_time_to_accuracy_is_the_last_entry_into_the_band():
+    h = [(100, 1.2), (200, 1.00005), (300, 1.0003), (400, 1.00002), (500, 0.99999)]
+    assert warmstart.time_to_accuracy(h, 1.0, 1e-4) == 400
+    assert warmstart.time_to_accuracy(h, 1.0, 1e-3) == 200
+    assert warmstart.time_to_accuracy(h, 1.0, 1e-6) == 500  # never inside: the last step
