@@ -238,11 +238,17 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
                      lbm_batch_t **out);
 void lbm_batch_destroy(lbm_batch_t *b);
 
-/* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups (0: one per
- * tile up to 2048), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW (default SHALLOW). */
+/* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups per kind
+ * (0: one per tile up to 2048; rounded down to a multiple of 8, each XCD walking its own eighth
+ * of the tile list), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW.  Default: tx = 256,
+ * groups = 0, flags = 0 (the fastest measured on the 64-lattice droplet sweep). */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 
-/* Segment height (rows per tile) of lattice i (default 32); the autotuner sets it per size. */
+/* Segment height (rows per tile) of lattice i; 0 (the default) is automatic: every time the
+ * tile list is rebuilt (lattices activated or dropped), the automatic lattices share one height,
+ * halved from 32 down to 4 rows until the active tiles number about 4096, so the lattices still
+ * running when most have converged spread over the whole GPU.  The autotuner sets it per size
+ * class.  Results do not depend on it (bitwise). */
 int lbm_batch_set_segment(lbm_batch_t *b, int i, int rows);
 
 /* f = f^eq(rho0, u0) for lattice i (host FP64 [ny][nx], u0 [ny][nx][2] or NULL); makes it

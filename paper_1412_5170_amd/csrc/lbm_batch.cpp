@@ -25,7 +25,8 @@ struct lbm_batch {
     int count = 0;
     std::vector<Physics> phys;
     std::vector<float *> f0, f1, vprev;
-    std::vector<int> seg_rows;       // segment height of each lattice's tiles
+    std::vector<int> seg_rows;       // segment height of each lattice's tiles (0: automatic)
+    int auto_rows = 32;              // segment height of the automatic lattices, per upload
     std::vector<char> active;
     std::vector<char> initialised;
     std::vector<long long> steps;
@@ -33,7 +34,8 @@ struct lbm_batch {
     std::vector<int> xa, ya, xb, yb;
     void *desc = nullptr;            // device BatchLattice[count]
     int4 *tiles = nullptr;           // device tile list (capacity max_tiles)
-    int *ntiles = nullptr;           // device tile count
+    int2 *meta = nullptr;            // device (offset, count) of each kind's tiles
+    std::vector<int> kinds;          // kinds present (scheme * 2 + collision), ascending
     size_t max_tiles = 0;
     // observables
     int4 *sblocks = nullptr;
@@ -42,7 +44,7 @@ struct lbm_batch {
     double *partial = nullptr, *out = nullptr;
     size_t max_sblocks = 0;
     // launch
-    int tx = 128, groups = 0, flags = pplbm::kFlagShallow;
+    int tx = 256, groups = 0, flags = 0;  // 256-column strips, two rows of loads in flight
     hipStream_t stream = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
@@ -63,9 +65,17 @@ int bfail(lbm_batch *b, int code, const std::string &m) {
         if (e_ != hipSuccess) return bfail(b, LBM_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-size_t tiles_of(const lbm_batch *b, int i) {
+constexpr int kAutoRowsMax = 32, kAutoRowsMin = 4;
+constexpr size_t kAutoTiles = 4096;  // ~16 workgroups per compute unit
+
+size_t tiles_at(const lbm_batch *b, int i, int rows) {
     const Physics &p = b->phys[i];
-    return (size_t)((p.nx + b->tx - 1) / b->tx) * ((p.ny + b->seg_rows[i] - 1) / b->seg_rows[i]);
+    return (size_t)((p.nx + b->tx - 1) / b->tx) * ((p.ny + rows - 1) / rows);
+}
+
+// Most tiles lattice i can ever have (capacity of the device tile list).
+size_t tiles_max(const lbm_batch *b, int i) {
+    return tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : kAutoRowsMin);
 }
 
 int upload_desc(lbm_batch *b) {
@@ -79,10 +89,14 @@ int upload_desc(lbm_batch *b) {
     return LBM_OK;
 }
 
-// Tile list of the active lattices (strips of tx columns x segments of seg_rows rows).
+// Tile list of the active lattices (strips of tx columns x segments of rows).  Lattices with
+// an automatic segment height share one, halved from 32 down to 4 rows until the active tiles
+// number about 4096: as converged lattices leave, the ones still running are cut finer, so a
+// lone large lattice still spreads over every compute unit.  (Tile shapes do not change the
+// results, which are bitwise those of any other shape.)
 int upload_tiles(lbm_batch *b) {
     size_t need = 0;
-    for (int i = 0; i < b->count; ++i) need += tiles_of(b, i);
+    for (int i = 0; i < b->count; ++i) need += tiles_max(b, i);
     if (need > b->max_tiles) {
         if (b->tiles) (void)hipFree(b->tiles);
         b->tiles = nullptr;
@@ -96,35 +110,52 @@ int upload_tiles(lbm_batch *b) {
             b->graph = nullptr;
         }
     }
+    b->auto_rows = kAutoRowsMax;
+    for (;;) {
+        size_t n = 0;
+        for (int i = 0; i < b->count; ++i)
+            if (b->active[i]) n += tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : b->auto_rows);
+        if (n >= kAutoTiles || b->auto_rows <= kAutoRowsMin) break;
+        b->auto_rows /= 2;
+    }
     std::vector<int4> t;
     t.reserve(need);
-    for (int i = 0; i < b->count; ++i) {
-        if (!b->active[i]) continue;
-        const Physics &p = b->phys[i];
-        const int H = b->seg_rows[i];
-        for (int y0 = 0; y0 < p.ny; y0 += H)
-            for (int x0 = 0; x0 < p.nx; x0 += b->tx) t.push_back(make_int4(i, x0, y0, H));
+    std::vector<int2> meta;
+    for (int kind : b->kinds) {  // tiles grouped by kind, one slice per kind
+        const int first = (int)t.size();
+        for (int i = 0; i < b->count; ++i) {
+            if (!b->active[i]) continue;
+            const Physics &p = b->phys[i];
+            if (p.scheme * 2 + p.coll != kind) continue;
+            const int H = b->seg_rows[i] ? b->seg_rows[i] : b->auto_rows;
+            for (int y0 = 0; y0 < p.ny; y0 += H)
+                for (int x0 = 0; x0 < p.nx; x0 += b->tx) t.push_back(make_int4(i, x0, y0, H));
+        }
+        meta.push_back(make_int2(first, (int)t.size() - first));
     }
-    const int n = (int)t.size();
-    if (n) BHIP(b, hipMemcpyAsync(b->tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->ntiles, &n, sizeof n, hipMemcpyHostToDevice, b->stream));
+    if (!t.empty())
+        BHIP(b, hipMemcpyAsync(b->tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->meta, meta.data(), meta.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     b->tiles_dirty = false;
     return LBM_OK;
 }
 
 int grid_groups(const lbm_batch *b) {
-    if (b->groups > 0) return b->groups;
+    if (b->groups > 0) return std::max(b->groups / 8 * 8, 8);
     size_t all = 0;
-    for (int i = 0; i < b->count; ++i) all += tiles_of(b, i);
-    const size_t g = std::min<size_t>(all, 2048);  // ~8 workgroups per compute unit
-    return (int)std::max<size_t>(g, 1);
+    for (int i = 0; i < b->count; ++i) all += tiles_max(b, i);
+    size_t g = std::min<size_t>(all, 2048);  // ~8 workgroups per compute unit
+    g = std::max<size_t>(g / 8 * 8, 8);      // a multiple of 8: each XCD walks its own eighth
+    return (int)g;
 }
 
 int launch_steps(lbm_batch *b, int n) {
     for (int k = 0; k < n; ++k)
-        BHIP(b, pplbm::launch_batch_sweep(b->desc, b->tiles, b->ntiles, k & 1, b->tx, grid_groups(b),
-                                          b->flags & pplbm::kFlagShallow, b->stream));
+        for (size_t j = 0; j < b->kinds.size(); ++j)
+            BHIP(b, pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
+                                             b->kinds[j] % 2, k & 1, b->tx, grid_groups(b),
+                                             b->flags & pplbm::kFlagShallow, b->stream));
     return LBM_OK;
 }
 
@@ -182,10 +213,13 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
             return rc;
         }
     }
+    for (int i = 0; i < count; ++i) b->kinds.push_back(b->phys[i].scheme * 2 + b->phys[i].coll);
+    std::sort(b->kinds.begin(), b->kinds.end());
+    b->kinds.erase(std::unique(b->kinds.begin(), b->kinds.end()), b->kinds.end());
     b->f0.assign(count, nullptr);
     b->f1.assign(count, nullptr);
     b->vprev.assign(count, nullptr);
-    b->seg_rows.assign(count, 32);
+    b->seg_rows.assign(count, 0);  // automatic
     b->active.assign(count, 0);
     b->initialised.assign(count, 0);
     b->steps.assign(count, 0);
@@ -208,7 +242,7 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
              hipMemsetAsync(b->f1[i], 0, fb, b->stream) == hipSuccess;
     }
     ok = ok && hipMalloc(&b->desc, pplbm::batch_lattice_bytes() * count) == hipSuccess &&
-         hipMalloc(&b->ntiles, sizeof(int)) == hipSuccess &&
+         hipMalloc(&b->meta, 8 * sizeof(int2)) == hipSuccess &&
          hipMalloc(&b->out, pplbm::kStatsOut * sizeof(double) * count) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -232,7 +266,7 @@ void lbm_batch_destroy(lbm_batch_t *b) {
         if (b->f1[i]) (void)hipFree(b->f1[i]);
         if (b->vprev[i]) (void)hipFree(b->vprev[i]);
     }
-    for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->ntiles, (void *)b->sblocks,
+    for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->meta, (void *)b->sblocks,
                     (void *)b->ranges, (void *)b->ids, (void *)b->partial, (void *)b->out})
         if (p) (void)hipFree(p);
     if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -257,7 +291,7 @@ int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags) {
 }
 
 int lbm_batch_set_segment(lbm_batch_t *b, int i, int rows) {
-    if (!b || i < 0 || i >= b->count || rows < 1) return LBM_EINVAL;
+    if (!b || i < 0 || i >= b->count || rows < 0) return LBM_EINVAL;
     b->seg_rows[i] = rows;
     return upload_tiles(b);
 }
@@ -448,7 +482,7 @@ int lbm_batch_autotune(lbm_batch_t *b, const char *cache_path, int trial_steps, 
         int tx = 0, fl = 0;
         std::vector<int> rows(distinct.size(), 32);
         bool ok = static_cast<bool>(in >> tx >> fl);
-        for (size_t c = 0; ok && c < distinct.size(); ++c) ok = static_cast<bool>(in >> rows[c]) && rows[c] >= 1;
+        for (size_t c = 0; ok && c < distinct.size(); ++c) ok = static_cast<bool>(in >> rows[c]) && rows[c] >= 0;
         if (ok && apply(tx, fl, rows) == LBM_OK) {
             if (ms_out) *ms_out = -1.0;
             return LBM_OK;

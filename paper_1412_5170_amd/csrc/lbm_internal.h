@@ -100,11 +100,13 @@ hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t strea
 size_t batch_lattice_bytes();
 void batch_lattice_fill(const Physics &p, float *f0, float *f1, float *vprev, int xa, int ya,
                         int xb, int yb, int flags, void *out);
-// One step of every lattice in the tile list: tiles[t] = (lattice, x0, y0, rows), *ntiles
-// entries, read from f[parity], written to f[parity ^ 1].  tx threads per workgroup, `groups`
-// persistent workgroups.
-hipError_t launch_batch_sweep(const void *lats, const int4 *tiles, const int *ntiles, int parity,
-                              int tx, int groups, bool shallow, hipStream_t stream);
+// One step of the batch lattices of one kind (`scheme`, `coll`; `kind` indexes meta): the tiles
+// tiles[meta[kind].x + t] = (lattice, x0, y0, rows), t < meta[kind].y, read from f[parity] and
+// written to f[parity ^ 1]; tx threads per workgroup, `groups` persistent workgroups.
+hipError_t launch_batch_kind(const void *lats, const int4 *tiles, const int2 *meta, int kind,
+                             int scheme, int coll, int parity, int tx, int groups, bool shallow,
+                             hipStream_t s);
+
 // Observables of the lattices listed in ids (nlat of them) from f[parity]: sblocks[b] =
 // (lattice, chunk, chunks, partial slot); ranges[i] = (first partial, count) of ids[i]; out
 // receives kStatsOut doubles per lattice id.

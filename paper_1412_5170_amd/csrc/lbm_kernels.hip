@@ -637,39 +637,28 @@ struct BatchLattice {
     int xa, ya, xb, yb;      // probe nodes
 };
 
-template <int PF>
-__global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchLattice *__restrict__ lats,
-                                                          const int4 *__restrict__ tiles,
-                                                          const int *__restrict__ ntiles,
-                                                          int parity) {
+// One kind of the batch (forcing scheme and collision): its tiles are the slice meta[kind] =
+// (offset, count) of the shared tile list, both read from device memory so that the host can
+// drop lattices between replays of a captured graph.  One specialised kernel per kind keeps the
+// register allocation of the single-lattice sweep (five waves per SIMD with one row of loads in
+// flight; the two-row variants of some kinds would spill at five, so they ask for four).
+template <int SCHEME, int COLL, int PF>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PF == 1 ? 5 : 4, 8)))
+batch_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict__ tiles,
+                  const int2 *__restrict__ meta, int kind, int parity) {
     extern __shared__ float ring[];
-    const int n = *ntiles;
-    for (int t = blockIdx.x; t < n; t += gridDim.x) {
-        const int4 tl = tiles[t];
+    const int2 m = meta[kind];
+    // Workgroups are dealt round-robin to the eight XCDs (the grid is a multiple of 8): XCD k
+    // walks the k-th contiguous eighth of the slice, so neighbouring tiles -- which share halo
+    // rows and columns -- meet in one L2.
+    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int begin = (int)((long long)m.y * xcd / 8), end = (int)((long long)m.y * (xcd + 1) / 8);
+    for (int t = begin + local; t < end; t += per) {
+        const int4 tl = tiles[m.x + t];
         const BatchLattice &L = lats[tl.x];
         const StepConst<float, double> c = L.c;
-        const float *fin = L.f[parity];
-        float *fout = L.f[parity ^ 1];
-        switch (L.scheme * 2 + L.coll) {
-        case EDM * 2 + BGK:
-            sweep_tile<float, double, EDM, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        case GUO * 2 + BGK:
-            sweep_tile<float, double, GUO, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        case GUO_LI * 2 + BGK:
-            sweep_tile<float, double, GUO_LI, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        case SC * 2 + BGK:
-            sweep_tile<float, double, SC, BGK, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        case GUO * 2 + MRT:
-            sweep_tile<float, double, GUO, MRT, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        default:
-            sweep_tile<float, double, GUO_LI, MRT, PF>(fin, fout, c, tl.y, tl.z, tl.w, ring);
-            break;
-        }
+        sweep_tile<float, double, SCHEME, COLL, PF>(L.f[parity], L.f[parity ^ 1], c, tl.y, tl.z,
+                                                    tl.w, ring);
         __syncthreads();  // the ring is reused by the next tile
     }
 }
@@ -1234,14 +1223,27 @@ void batch_lattice_fill(const Physics &p, float *f0, float *f1, float *vprev, in
     *reinterpret_cast<BatchLattice *>(out) = L;
 }
 
-hipError_t launch_batch_sweep(const void *lats, const int4 *tiles, const int *ntiles, int parity,
-                              int tx, int groups, bool shallow, hipStream_t s) {
+hipError_t launch_batch_kind(const void *lats, const int4 *tiles, const int2 *meta, int kind,
+                             int scheme, int coll, int parity, int tx, int groups, bool shallow,
+                             hipStream_t s) {
     const size_t lds = 4 * (size_t)(tx + 2) * sizeof(float);
     const BatchLattice *L = reinterpret_cast<const BatchLattice *>(lats);
-    if (shallow)
-        hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3(groups), dim3(tx), lds, s, L, tiles, ntiles, parity);
-    else
-        hipLaunchKernelGGL(batch_sweep_kernel<2>, dim3(groups), dim3(tx), lds, s, L, tiles, ntiles, parity);
+    const dim3 g(groups), blk(tx);
+#define PPLBM_KIND(S, C)                                                                         \
+    if (shallow)                                                                                 \
+        hipLaunchKernelGGL((batch_kind_kernel<S, C, 1>), g, blk, lds, s, L, tiles, meta, kind, parity); \
+    else                                                                                         \
+        hipLaunchKernelGGL((batch_kind_kernel<S, C, 2>), g, blk, lds, s, L, tiles, meta, kind, parity)
+    switch (scheme * 2 + coll) {
+    case EDM * 2 + BGK: PPLBM_KIND(EDM, BGK); break;
+    case GUO * 2 + BGK: PPLBM_KIND(GUO, BGK); break;
+    case GUO_LI * 2 + BGK: PPLBM_KIND(GUO_LI, BGK); break;
+    case SC * 2 + BGK: PPLBM_KIND(SC, BGK); break;
+    case GUO * 2 + MRT: PPLBM_KIND(GUO, MRT); break;
+    case GUO_LI * 2 + MRT: PPLBM_KIND(GUO_LI, MRT); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef PPLBM_KIND
     return hipGetLastError();
 }
 

@@ -324,7 +324,7 @@ class Batch:
     ny, T_over_Tc, K, scheme, A, sigma, collision, s (5 MRT rates), tau; "psi_eps" (with "G")
     selects the effective density of Eq. 33 instead of the Carnahan-Starling EOS."""
 
-    def __init__(self, members, tx=128, groups=0, flags=LBM_LAUNCH_SHALLOW):
+    def __init__(self, members, tx=256, groups=0, flags=0):
         n = len(members)
         self.members = members
         nx = (ctypes.c_int * n)(*[m["nx"] for m in members])

@@ -101,13 +101,13 @@ def run_to_equilibrium(b, tol, tol_rho=0.0, check_every=100, max_steps=400_000,
         cap = min(cap + chunk, max_steps)
 
 
-def run_batch(lbm, members, inits, tol=1e-9, check_every=100, max_steps=400_000, tx=128,
-              segment=None, tol_rho=0.0, chunk=None, report=None):
+def run_batch(lbm, members, inits, tol=1e-9, check_every=100, max_steps=400_000, tx=256,
+              segment=None, tol_rho=0.0, chunk=None, report=None, flags=None):
     """Advance all members to equilibrium (velocity change per step < tol and, if tol_rho > 0,
     relative change per step of the probe densities < tol_rho).  inits[i] is a density array
     or a WarmStart; either starts at physical rest (v = 0).  Returns wall seconds, steps,
     statuses and the batch (its `fallbacks` counts warm starts that fell back)."""
-    b = lbm.Batch(members, tx=tx)
+    b = lbm.Batch(members, tx=tx) if flags is None else lbm.Batch(members, tx=tx, flags=flags)
     b.lbm = lbm
     b.fallbacks = 0
     for i, init in enumerate(inits):
@@ -147,6 +147,8 @@ def main(argv=None):
     ap.add_argument("--check-every", type=int, default=500)
     ap.add_argument("--max-steps", type=int, default=1_000_000)
     ap.add_argument("--chunk", type=int, default=20_000)
+    ap.add_argument("--tx", type=int, default=256, help="strip width of the batch tiles")
+    ap.add_argument("--flags", type=int, default=None, help="batch launch flags")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from . import lbm
@@ -159,7 +161,7 @@ def main(argv=None):
     inits = [tanh_density(lbm, m) for m in members]
     wall, steps, status, b = run_batch(lbm, members, inits, tol=a.tol, tol_rho=a.tol_rho,
                                        check_every=a.check_every, max_steps=a.max_steps,
-                                       chunk=a.chunk, report=say)
+                                       chunk=a.chunk, report=say, tx=a.tx, flags=a.flags)
     lu = sum(m["nx"] * m["ny"] * s for m, s in zip(members, steps))
     res = {"wall_s": round(wall, 2), "lattice_updates": int(lu),
            "glups": round(lu / wall / 1e9, 2), "converged": int(sum(s == 0 for s in status)),
