@@ -200,6 +200,13 @@ int lbm_populations(lbm_t *h, float *f);
 /* Replace the populations from a host FP32 array [9][ny][nx]; keeps the step count. */
 int lbm_set_populations(lbm_t *h, const float *f);
 
+/* Checkpoint: lbm_save writes the populations (FP32), the step count and the parameter structs
+ * to `path`; lbm_load restores them into a handle created with the same size and parameters
+ * (LBM_EINVAL otherwise, or for a file this library did not write).  Both synchronise.  The
+ * file holds native-endian binary data. */
+int lbm_save(lbm_t *h, const char *path);
+int lbm_load(lbm_t *h, const char *path);
+
 /* FP64 observables of the current state.  track_dv != 0 also compares v with the velocity
  * stored by the previous tracked call (dv_max; 0 on the first) and stores the current one.
  * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. Synchronises. */
@@ -262,6 +269,12 @@ int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0);
  * impulse whose ringing sets the time to equilibrium even from an exact equilibrium density.
  * Makes the lattice active and resets its step count.  Synchronises. */
 int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0);
+
+/* The plain start of the droplet sweeps: rho = (rho_in + rho_out)/2 - (rho_in - rho_out)/2
+ * tanh(2 (r - R) / W), r the distance from (nx/2, ny/2), with the Maxwell densities of the
+ * lattice's EOS (lbm_coexistence) -- liquid inside for droplet != 0, gas inside (a bubble)
+ * otherwise -- set at physical rest as in lbm_batch_init_rest.  Synchronises. */
+int lbm_batch_init_tanh(lbm_batch_t *b, int i, double R, double W, int droplet);
 
 /* Warm start of lattice i from a radial profile (the learned initial state): log_rho holds 64
  * host values of log rho at the radii r_k = r0 + k dr (k = 0..63, dr > 0), r the distance from

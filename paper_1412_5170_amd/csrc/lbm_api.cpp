@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -627,6 +628,89 @@ int lbm_read(lbm_t *h, double *rho, double *u) {
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return hip_fail(h, e, "lbm_read");
+    return LBM_OK;
+}
+
+// Checkpoint file: "PPLBMCK1", int32 nx, ny, int64 step, the parameter structs as written by
+// this library (eos, force, collision, tau), then FP32 populations [9][ny][nx].
+namespace {
+constexpr char kCkptMagic[8] = {'P', 'P', 'L', 'B', 'M', 'C', 'K', '1'};
+
+// Field by field (the structs have padding).
+bool same_params(const lbm_eos &a, const lbm_eos &b, const lbm_force &fa, const lbm_force &fb,
+                 const lbm_collision &ca, const lbm_collision &cb) {
+    return a.kind == b.kind && a.a == b.a && a.b == b.b && a.R == b.R && a.T_over_Tc == b.T_over_Tc &&
+           a.K == b.K && a.eps == b.eps && fa.scheme == fb.scheme && fa.A == fb.A &&
+           fa.sigma == fb.sigma && fa.G == fb.G && ca.kind == cb.kind && ca.s_rho == cb.s_rho &&
+           ca.s_e == cb.s_e && ca.s_eps == cb.s_eps && ca.s_j == cb.s_j && ca.s_q == cb.s_q;
+}
+}  // namespace
+
+int lbm_save(lbm_t *h, const char *path) {
+    if (!h || !path) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_save before lbm_init");
+    const size_t n = 9 * (size_t)h->p.nx * h->p.ny;
+    std::vector<float> f;
+    try {
+        f.resize(n);
+    } catch (...) {
+        return fail(h, LBM_ENOMEM, "checkpoint staging buffer");
+    }
+    int rc = lbm_populations(h, f.data());
+    if (rc) return rc;
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(h, LBM_EINVAL, std::string("cannot open ") + path);
+    const int32_t dims[2] = {h->p.nx, h->p.ny};
+    const int64_t step = h->step;
+    bool ok = std::fwrite(kCkptMagic, 1, 8, fp) == 8 && std::fwrite(dims, sizeof dims, 1, fp) == 1 &&
+              std::fwrite(&step, sizeof step, 1, fp) == 1 &&
+              std::fwrite(&h->eos, sizeof h->eos, 1, fp) == 1 &&
+              std::fwrite(&h->force, sizeof h->force, 1, fp) == 1 &&
+              std::fwrite(&h->coll, sizeof h->coll, 1, fp) == 1 &&
+              std::fwrite(&h->tau, sizeof h->tau, 1, fp) == 1 &&
+              std::fwrite(f.data(), sizeof(float), n, fp) == n;
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? LBM_OK : fail(h, LBM_EINVAL, std::string("write failed: ") + path);
+}
+
+int lbm_load(lbm_t *h, const char *path) {
+    if (!h || !path) return LBM_EINVAL;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return fail(h, LBM_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t dims[2];
+    int64_t step = 0;
+    lbm_eos eos;
+    lbm_force force;
+    lbm_collision coll;
+    double tau = 0;
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0 &&
+              std::fread(dims, sizeof dims, 1, fp) == 1 && std::fread(&step, sizeof step, 1, fp) == 1 &&
+              std::fread(&eos, sizeof eos, 1, fp) == 1 && std::fread(&force, sizeof force, 1, fp) == 1 &&
+              std::fread(&coll, sizeof coll, 1, fp) == 1 && std::fread(&tau, sizeof tau, 1, fp) == 1;
+    if (!ok) {
+        std::fclose(fp);
+        return fail(h, LBM_EINVAL, "not a checkpoint of this library");
+    }
+    if (dims[0] != h->p.nx || dims[1] != h->p.ny ||
+        !same_params(eos, h->eos, force, h->force, coll, h->coll) || tau != h->tau) {
+        std::fclose(fp);
+        return fail(h, LBM_EINVAL, "checkpoint of another lattice (size or parameters differ)");
+    }
+    const size_t n = 9 * (size_t)h->p.nx * h->p.ny;
+    std::vector<float> f;
+    try {
+        f.resize(n);
+    } catch (...) {
+        std::fclose(fp);
+        return fail(h, LBM_ENOMEM, "checkpoint staging buffer");
+    }
+    ok = std::fread(f.data(), sizeof(float), n, fp) == n;
+    std::fclose(fp);
+    if (!ok) return fail(h, LBM_EINVAL, "truncated checkpoint");
+    int rc = lbm_set_populations(h, f.data());
+    if (rc) return rc;
+    h->step = step;
     return LBM_OK;
 }
 

@@ -24,6 +24,8 @@ using pplbm::Physics;
 struct lbm_batch {
     int count = 0;
     std::vector<Physics> phys;
+    std::vector<lbm_eos> eos;        // as given (Maxwell densities of the plain start)
+    std::vector<lbm_force> force;
     std::vector<float *> f0, f1, vprev;
     std::vector<int> seg_rows;       // segment height of each lattice's tiles (0: automatic)
     int auto_rows = 32;              // segment height of the automatic lattices, per upload
@@ -203,6 +205,8 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
     if (!b) return LBM_ENOMEM;
     b->count = count;
     b->phys.resize(count);
+    b->eos.assign(eos, eos + count);
+    b->force.assign(force, force + count);
     for (int i = 0; i < count; ++i) {
         std::string why;
         int rc = pplbm::make_physics(nx[i], ny[i], &eos[i], &force[i], &coll[i], tau[i], &b->phys[i],
@@ -352,6 +356,23 @@ int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0) {
     rc = rest_state(b, i);
     if (rc) b->initialised[i] = b->active[i] = 0;
     return rc ? rc : upload_tiles(b);
+}
+
+int lbm_batch_init_tanh(lbm_batch_t *b, int i, double R, double W, int droplet) {
+    if (!b || i < 0 || i >= b->count || !(R > 0) || !(W > 0)) return LBM_EINVAL;
+    double g = 0, l = 0;
+    int rc = lbm_coexistence(&b->eos[i], &b->force[i], LBM_COEX_MAXWELL, 0.0, &g, &l);
+    if (rc) return bfail(b, rc, "no coexistence densities for this lattice's EOS");
+    const Physics &p = b->phys[i];
+    const double in = droplet ? l : g, out = droplet ? g : l;
+    std::vector<double> rho((size_t)p.nx * p.ny);
+    for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+            const double dx = x - 0.5 * p.nx, dy = y - 0.5 * p.ny;
+            const double r = std::sqrt(dx * dx + dy * dy);
+            rho[(size_t)y * p.nx + x] = 0.5 * (in + out) - 0.5 * (in - out) * std::tanh(2 * (r - R) / W);
+        }
+    return lbm_batch_init_rest(b, i, rho.data());
 }
 
 int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double r0, double dr,

@@ -233,6 +233,14 @@ class Lattice:
         check(lbm_populations(self.h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.h)
         return f
 
+    def save(self, path):
+        """Checkpoint (populations, step count, parameters) to a file."""
+        check(lbm_save(self.h, os.fsencode(path)), self.h)
+
+    def load(self, path):
+        """Restore a checkpoint written by `save` for a lattice of the same size and parameters."""
+        check(lbm_load(self.h, os.fsencode(path)), self.h)
+
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float32)
         assert f.shape == (9, self.ny, self.nx)
@@ -292,6 +300,10 @@ _BSIG = {
     "lbm_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int, _D]),
     "lbm_batch_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int, _D]),
     "lbm_batch_init_rest": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "lbm_batch_init_tanh": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int]),
+    "lbm_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "lbm_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "lbm_batch_init_profile": (ctypes.c_int, [_P, ctypes.c_int, _D, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double, _D]),
     "lbm_batch_set_active": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -365,6 +377,11 @@ class Batch:
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
         assert rho0.shape == (m["ny"], m["nx"])
         bcheck(lbm_batch_init_rest(self.b, i, _dptr(rho0)), self.b)
+
+    def init_tanh(self, i, R, W=5.0, droplet=True):
+        """The plain start: a tanh droplet (or bubble) of radius R between the Maxwell densities
+        of the lattice's EOS, at physical rest."""
+        bcheck(lbm_batch_init_tanh(self.b, i, float(R), float(W), int(droplet)), self.b)
 
     def init_profile(self, i, log_rho, r0, dr, mass=0.0):
         """Warm start from 64 values of log rho at r_k = r0 + k dr; with mass > 0 the profile is

@@ -149,3 +149,18 @@ def test_create_accepts_sc_and_eq33_and_rejects_sc_mrt():
     bad = lbm.make_ss_eos(-1.0)
     assert ok(8, 8, ctypes.byref(bad), ctypes.byref(lbm.make_force("GUO", G=-3.0)),
               ctypes.byref(coll), 1.0, ctypes.byref(h)) == lbm.LBM_EINVAL
+
+
+def test_load_rejects_missing_and_foreign_files(tmp_path):
+    from paper_1412_5170_amd import lbm
+    h = lbm._P()
+    eos, frc, coll = lbm.make_eos(0.7), lbm.make_force("GUO"), lbm.make_collision("BGK")
+    assert lbm.lbm_create(8, 8, ctypes.byref(eos), ctypes.byref(frc), ctypes.byref(coll), 1.0,
+                          ctypes.byref(h)) == lbm.LBM_OK
+    try:
+        assert lbm.lbm_load(h, os.fsencode(str(tmp_path / "missing.ckpt"))) == lbm.LBM_EINVAL
+        bad = tmp_path / "bad.ckpt"
+        bad.write_bytes(b"NOTACKPT" + bytes(64))
+        assert lbm.lbm_load(h, os.fsencode(str(bad))) == lbm.LBM_EINVAL
+    finally:
+        lbm.lbm_destroy(h)
