@@ -232,3 +232,53 @@ def test_sweep_parity_100_steps(L):
     e_rho, e_v = errors(*lat.read(), fl)
     say(f"    rho {e_rho:.3e}  v {e_v:.3e}")
     assert e_rho < TOL and e_v < TOL
+
+
+def test_full_size_4096_sampled_windows(L):
+    """The timed workload at its full size (4096 x 4096 droplet, R = 600, T/Tc = 0.5, MRT with
+    Guo + Li forcing, mixed precision) in the library's default launch, against the oracle on
+    sampled windows.  One step moves information at most two nodes (streaming, plus the psi
+    stencil of the force), so after K steps a window depends only on the nodes within 2K of
+    it: the oracle runs the patch with a margin of 2K + 1 around each window, mirrored into a
+    2 x 2 periodic tile so that its seams are continuous (a plain wrap would join liquid to
+    gas and blow up); nothing from the seams reaches the window.  Windows: the interface on
+    both axes and the diagonal (one of them on a strip and segment corner of the default
+    launch) and the corner where the lattice wraps."""
+    wl = workload("droplet_4096_mrt")
+    K, win = 100, 16
+    margin = 2 * K + 1
+    say(f"[parity full size] {wl['nx']}x{wl['ny']} mixed default launch, {K} steps")
+    rho0 = initial_density(wl)
+    lat = gpu_lattice(L, wl, PRECISIONS["mixed"])
+    lat.init(rho0)
+    lat.step(K)
+    rho_g, u_g = lat.read()
+    nx, ny = wl["nx"], wl["ny"]
+    c = nx // 2
+    R = wl["R"]
+    starts = [(c + int(R) - win // 2, c - win // 2),                  # interface, +x
+              (c - win // 2, c - int(R) - win // 2),                  # interface, -y
+              (c + int(R / 2 ** 0.5) - win // 2, c + int(R / 2 ** 0.5) - win // 2),
+              (c - win // 2, c + int(R) - win // 2),                  # interface, +y, on a
+                                                                      # strip and segment corner
+              (nx - win // 2, ny - win // 2)]                         # periodic wrap
+    e_rho, dv, vref = 0.0, 0.0, 0.0
+    for x0, y0 in starts:
+        n = win + 2 * margin
+        xs = np.arange(x0 - margin, x0 - margin + n) % nx
+        ys = np.arange(y0 - margin, y0 - margin + n) % ny
+        P = rho0[np.ix_(ys, xs)]
+        Q = np.block([[P, P[:, ::-1]], [P[::-1, :], P[::-1, ::-1]]])
+        p = oracle_params(dict(wl, nx=2 * n, ny=2 * n))
+        fl = O.fields(p, O.step(p, O.init_feq(Q), K))
+        inner = np.s_[margin:margin + win, margin:margin + win]
+        wy, wx = np.ix_(ys[margin:margin + win], xs[margin:margin + win])
+        r_o, vx_o, vy_o = fl["rho"][inner], fl["vx"][inner], fl["vy"][inner]
+        e = float(np.max(np.abs(rho_g[wy, wx] - r_o) / r_o))
+        d = max(np.abs(u_g[wy, wx, 0] - vx_o).max(), np.abs(u_g[wy, wx, 1] - vy_o).max())
+        say(f"    window at ({x0 % nx}, {y0 % ny}): rho {e:.3e}  |dv| {d:.3e}  "
+            f"max |v| {max(np.abs(vx_o).max(), np.abs(vy_o).max()):.3e}")
+        e_rho, dv = max(e_rho, e), max(dv, d)
+        vref = max(vref, np.abs(vx_o).max(), np.abs(vy_o).max())
+    say(f"    all windows: rho {e_rho:.3e}  v {dv / vref:.3e}")
+    assert e_rho < TOL and dv / vref < TOL

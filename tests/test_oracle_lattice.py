@@ -174,3 +174,34 @@ def test_sigma_zero_reduces_li_to_guo(oracle, thermo):
         a = O.step(_params(O, thermo, scheme=O.GUO_LI, sigma=0.0, **kw), f, 2)
         b = O.step(_params(O, thermo, scheme=O.GUO, **kw), f, 2)
         assert np.array_equal(a, b)
+
+
+def test_window_depends_only_on_its_2k_neighbourhood(oracle, thermo):
+    """Domain of dependence used by the full-size sampled parity test: after K steps a node
+    depends only on nodes within 2K (one for streaming, one for the psi stencil of the force
+    per step).  A window computed from its mirrored neighbourhood with a margin of 2K + 1 must
+    equal, bit for bit, the same window of the whole periodic lattice."""
+    O = oracle
+    nx = ny = 96
+    K, win = 6, 8
+    margin = 2 * K + 1
+    g, l, _ = thermo.maxwell(0.6)
+    rho0 = inputs.droplet(nx, ny, 24.0, 3.0, l, g)
+    s = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 1.0, 1.0)
+    kw = dict(T=thermo.temperature(0.6), tau=1.0, K=1.0, A=0.0, sigma=0.125,
+              scheme=O.GUO_LI, collision=O.MRT, s=s)
+    full = O.fields(O.Params(nx=nx, ny=ny, **kw), O.step(O.Params(nx=nx, ny=ny, **kw),
+                                                         O.init_feq(rho0), K))
+    for x0, y0 in [(48 + 24 - 4, 44), (90, 92)]:
+        n = win + 2 * margin
+        xs = np.arange(x0 - margin, x0 - margin + n) % nx
+        ys = np.arange(y0 - margin, y0 - margin + n) % ny
+        P = rho0[np.ix_(ys, xs)]
+        Q = np.block([[P, P[:, ::-1]], [P[::-1, :], P[::-1, ::-1]]])
+        p = O.Params(nx=2 * n, ny=2 * n, **kw)
+        fl = O.fields(p, O.step(p, O.init_feq(Q), K))
+        inner = np.s_[margin:margin + win, margin:margin + win]
+        wy, wx = np.ix_(ys[margin:margin + win], xs[margin:margin + win])
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(fl[k][inner], full[k][wy, wx]), (x0, y0, k)
+        assert np.abs(full["vx"][wy, wx]).max() > 1e-6 or (x0, y0) == (90, 92)
