@@ -6,6 +6,7 @@ torch provides device memory and the stream (``Lattice``); nothing falls back to
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -69,6 +70,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_5170_amd.build` "
                       "(there is no CPU fallback)")
 _lib = ctypes.CDLL(LIB_PATH)
+
+# Objects still alive when the interpreter exits are not destroyed through the library: the
+# module's globals and the HIP runtime may already be gone, and the process frees everything.
+_LIVE = [True]
+atexit.register(_LIVE.__setitem__, 0, False)
 
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -207,9 +213,9 @@ class Lattice:
         if tile is not None:
             check(lbm_set_tile(h, *tile), h)
 
-    def __del__(self):
+    def __del__(self, _live=_LIVE):
         h = getattr(self, "h", None)
-        if h:
+        if h and _live[0]:
             lbm_destroy(h)
             self.h = None
 
@@ -355,9 +361,9 @@ class Batch:
         self.b = b
         bcheck(lbm_batch_set_launch(b, tx, groups, flags), b)
 
-    def __del__(self):
+    def __del__(self, _live=_LIVE):
         b = getattr(self, "b", None)
-        if b:
+        if b and _live[0]:
             lbm_batch_destroy(b)
             self.b = None
 
@@ -480,9 +486,9 @@ class MLP:
             parts += [rng.uniform(-lim, lim, size=o * i), np.zeros(o)]
         self.set_params(np.concatenate(parts).astype(np.float32))
 
-    def __del__(self):
+    def __del__(self, _live=_LIVE):
         n = getattr(self, "n", None)
-        if n:
+        if n and _live[0]:
             lbm_mlp_destroy(n)
             self.n = None
 
