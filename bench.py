@@ -9,8 +9,8 @@ populations, force, forcing, collision and streaming in one launch); --kernel tw
 density/psi pass and the fused pass instead -- and the FP64 observables reduction runs every
 --stats-every steps inside the timed region, as a production run would.  Inputs are resident in
 HBM before timing starts.  The sweep runs the library's default launch
-(256-column strips, 8-row segments, two rows of loads in flight, XCD-ordered tiles: the
-fastest shape measured on this workload); --autotune lets the library's autotuner pick
+(512-column strips, 8-row segments, two rows of loads in flight, XCD-ordered tiles: the
+fastest shape measured on this workload and on 2048^2 to 8192^2 lattices); --autotune lets the library's autotuner pick
 (timed trials on the initial state, which it restores, before the warm-up), --launch sets it.
 
 Prints ONE JSON line: MLUPS, the HBM roofline of the dominant kernel measured with HIP events
@@ -214,7 +214,7 @@ def main():
           f"ratio {st['ratio']:.2f}", file=sys.stderr, flush=True)
     del lat
 
-    def roofline(kernel, ev):
+    def roofline(kernel, ev, launch):
         psi_ms, main_ms, nt = ev
         avg = main_ms / 1e3 / nt
         per_node = SWEEP_BYTES_PER_NODE if kernel == "sweep" else FUSED_BYTES_PER_NODE
@@ -230,8 +230,9 @@ def main():
         if os.path.exists(PROFILE_TRAFFIC):
             t = json.load(open(PROFILE_TRAFFIC))
             key = f"{args.workload}/{kernel}/{args.precision}/{args.layout}"
-            # Counters are only valid for the kernel source they were taken on.
-            if key in t and t[key]["kernel_sha256_16"] == kernel_source_hash():
+            # Counters are only valid for the kernel source and launch they were taken on.
+            if (key in t and t[key]["kernel_sha256_16"] == kernel_source_hash()
+                    and list(t[key].get("launch", [])) == list(launch)):
                 r["traffic"] = t[key]["bytes_per_launch"]
                 r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] /
                                                       (per_node * nodes), 4)
@@ -250,17 +251,18 @@ def main():
                    "kernel": args.kernel, "launch": list(launch),
                    "autotuned": tuned_ms is not None, "layout": args.layout,
                    "stats_every": args.stats_every, "parallelism": "single GPU"},
-        "roofline": roofline(args.kernel, ev) if ev else None,
+        "roofline": roofline(args.kernel, ev, launch) if ev else None,
     }
     alt = "two_pass" if args.kernel == "sweep" else "sweep"
     if timing and args.alt_steps:
         lat = make_lattice(lbm, wl, args, alt)
+        alt_launch = lat.get_launch()
         lat.init(rho0)
         lat.step(args.warmup)
         el2, ev2 = timed(lat, args.alt_steps, args.stats_every, torch, True)
         del lat
         out["alternative"] = {"kernel": alt, "MLUPS": round(nodes * args.alt_steps / el2 / 1e6, 1),
-                              "roofline": roofline(alt, ev2)}
+                              "roofline": roofline(alt, ev2, alt_launch)}
     del rho0
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -156,8 +156,9 @@ int lbm_set_layout(lbm_t *h, int layout);
 int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
- * the sweep with tx <= 256, ty <= 32 shrunk until the launch has ~1024 workgroups, flags
- * LBM_LAUNCH_XCD_ORDER | LBM_LAUNCH_SHALLOW.
+ * the sweep with tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER,
+ * narrowed (tx, then ty) on small lattices until the launch has about 1024 workgroups; a
+ * lattice whose population buffer exceeds 4 GiB uses the two-pass kernel (256 x 4).
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
  *     reads it; (tx, ty) = threads per workgroup of the fused pass (tx a multiple of 64,
  *     tx * ty <= 1024).  116 bytes of memory traffic per node and step.

@@ -169,7 +169,7 @@ pplbm::Launch default_launch(int nx, int ny) {
     pplbm::Launch L;
     L.kernel = pplbm::kKernelSweep;
     L.flags = pplbm::kFlagXCD;
-    L.tx = 256;
+    L.tx = 512;
     L.ty = 8;
     auto groups = [&]() { return (double)((nx + L.tx - 1) / L.tx) * ((ny + L.ty - 1) / L.ty); };
     while (groups() < 1024 && (L.tx > 64 || L.ty > 4)) {

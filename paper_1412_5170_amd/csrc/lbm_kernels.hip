@@ -113,15 +113,17 @@ struct StepConst {
     D kguo;   // 1 - 1/(2 tau)   (Eq. 23)
     R li;     // sigma / (tau - 1/2): v' = v + li F / psi^2 (Eq. 31)
     R li2;    // 2 sigma: Li's extra stress X = li2 F F / psi^2 (MRT form)
-    D s[9];   // MRT rates in moment order
-    D hs[9];  // 1 - s/2
+    D sd[9];  // MRT rates in moment order over the squared norms of M's rows (M^-1 = M^T D^-1)
+    D hd[9];  // (1 - s/2) over the same norms
     R lim[9]; // 1 / (1/s_k - 1/2) for the moments that carry Li's stress
 
-    __device__ __forceinline__ float psi_of(const float f[9]) const {
-        const D rho = density9<D>(f);
+    __device__ __forceinline__ float psi_of_rho(D rho) const {
         if (psi_kind == 0) return (float)eos_psi<D>(rho, bq, RT, a, K, two_over_G);
         // Eq. 33 in the shape precision R (FP32 in the mixed path): psi is stored in FP32.
         return (float)ss_psi<R>((R)rho, (R)inv_eps);
+    }
+    __device__ __forceinline__ float psi_of(const float f[9]) const {
+        return psi_of_rho(density9<D>(f));
     }
 };
 
@@ -187,7 +189,7 @@ __device__ __forceinline__ void guo_bracket(R Fx, R Fy, R Vx, R Vy, R B[9]) {
 // populations of the node; fs receives the post-collision ones (FP32, ready to store).
 template <typename R, typename D, int SCHEME, int COLL>
 __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
-                                        const StepConst<R, D> &c, float fs[9]) {
+                                        const StepConst<R, D> &c, float fs[9], D rho_d) {
     // Eq. 6 with w(1) = 1/3, w(2) = 1/12: link sums as differences of opposite pairs.  In D:
     // in the light phase u and F/(2 rho) nearly cancel in v, so F and u must be accurate.
     const D third = D(1) / D(3), twelfth = D(1) / D(12);
@@ -207,15 +209,16 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         Fyd += c.gA * s2y;
     }
 
-    // Eq. 3, u = sum f e / rho, v = u + F / (2 rho).  Momentum from opposite-pair differences.
-    const D rho_d = density9<D>(f);
+    // Eq. 3 (rho_d = density9<D>(f), passed in: the sweep has it from the node's psi),
+    // u = sum f e / rho, v = u + F / (2 rho).  Momentum from opposite-pair differences.
     const D jx = (((D)f[1] - (D)f[3]) + ((D)f[5] - (D)f[7])) + ((D)f[8] - (D)f[6]);
     const D jy = (((D)f[2] - (D)f[4]) + ((D)f[5] - (D)f[7])) + ((D)f[6] - (D)f[8]);
     const D inv = recip<D>(rho_d), hinv = D(0.5) * inv;
     const D uxd = jx * inv, uyd = jy * inv;
+    const D vxd = uxd + Fxd * hinv, vyd = uyd + Fyd * hinv;
     const R rho = (R)rho_d;
     const R ux = (R)uxd, uy = (R)uyd;
-    const R vx = (R)(uxd + Fxd * hinv), vy = (R)(uyd + Fyd * hinv);
+    const R vx = (R)vxd, vy = (R)vyd;
     const R Fx = (R)Fxd, Fy = (R)Fyd;
     const R pc = p.c;
 
@@ -258,23 +261,26 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         }
     } else {
         // MRT, Eq. 34: m* = m - Lambda (m - m_eq) + (I - Lambda/2) S with m_eq = M f^eq(rho, v).
-        // Evaluated as f* = f + M^-1 [Lambda M (f^eq - f) + (I - Lambda/2) S] so that only
-        // non-equilibrium quantities go through the transform.
-        D d[9];
-        eq_minus_f<R, D>(rho_d, vx, vy, f, d);  // d = f^eq - f
-        const D ax = d[1] + d[2] + d[3] + d[4], dg = d[5] + d[6] + d[7] + d[8];
-        const D d13 = d[1] - d[3], d24 = d[2] - d[4], d57 = d[5] - d[7], d86 = d[8] - d[6],
-                d68 = d[6] - d[8];
-        D n[9];  // M (f^eq - f)
-        n[0] = (d[0] + ax) + dg;
-        n[1] = -D(4) * d[0] - ax + D(2) * dg;
-        n[2] = D(4) * d[0] - D(2) * ax + dg;
-        n[3] = d13 + d57 + d86;
-        n[4] = -D(2) * d13 + d57 + d86;
-        n[5] = d24 + d57 + d68;
-        n[6] = -D(2) * d24 + d57 + d68;
-        n[7] = (d[1] + d[3]) - (d[2] + d[4]);
-        n[8] = (d[5] + d[7]) - (d[6] + d[8]);
+        // Evaluated as f* = f + M^-1 [Lambda (m_eq - m) + (I - Lambda/2) S] so that only
+        // non-equilibrium quantities go through the inverse transform.  m_eq has the closed form
+        // rho (1, -2 + 3 v.v, 1 - 3 v.v, v_x, -v_x, v_y, -v_y, v_x^2 - v_y^2, v_x v_y) of the
+        // moments of Eq. 2; each difference is written on the populations' deviation from the
+        // rest state, and rho v = j + F/2 fixes the momentum rows exactly.
+        const D f0 = f[0], ax = ((D)f[1] + (D)f[2]) + ((D)f[3] + (D)f[4]);
+        const D dg = ((D)f[5] + (D)f[6]) + ((D)f[7] + (D)f[8]);
+        const D d13 = (D)f[1] - (D)f[3], d24 = (D)f[2] - (D)f[4];
+        const D rv2 = rho_d * (vxd * vxd + vyd * vyd);
+        const D hFx = D(0.5) * Fxd, hFy = D(0.5) * Fyd;
+        D n[9];  // m_eq - m
+        n[0] = D(0);                                           // mass is conserved
+        n[1] = (D(3) * rv2 + D(2) * f0) - (ax + D(4) * dg);    // e
+        n[2] = D(3) * ((ax - f0) - rv2);                       // epsilon
+        n[3] = hFx;                                            // j_x
+        n[4] = (D(3) * d13 - D(2) * jx) - hFx;                 // q_x
+        n[5] = hFy;                                            // j_y
+        n[6] = (D(3) * d24 - D(2) * jy) - hFy;                 // q_y
+        n[7] = rho_d * ((vxd - vyd) * (vxd + vyd)) - (((D)f[1] + (D)f[3]) - ((D)f[2] + (D)f[4]));
+        n[8] = rho_d * (vxd * vyd) - (((D)f[5] + (D)f[7]) - ((D)f[6] + (D)f[8]));
         // Guo's source in moment space, S = M B(v).
         const R vF = vx * Fx + vy * Fy;
         R S[9] = {R(0), R(6) * vF, -R(6) * vF, Fx, -Fx, Fy, -Fy,
@@ -288,11 +294,10 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
             S[7] += (Xxx - Xyy) * c.lim[7];
             S[8] += Xxy * c.lim[8];
         }
-        D a[9];  // D^-1 [Lambda M (f^eq - f) + (I - Lambda/2) S]
-        const D Dinv[9] = {D(1) / D(9), D(1) / D(36), D(1) / D(36), D(1) / D(6), D(1) / D(12),
-                           D(1) / D(6), D(1) / D(12), D(1) / D(4), D(1) / D(4)};
+        D a[9];  // D^-1 [Lambda (m_eq - m) + (I - Lambda/2) S]; row 0 vanishes (n_0 = S_0 = 0)
+        a[0] = D(0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) a[k] = (c.s[k] * n[k] + c.hs[k] * (D)S[k]) * Dinv[k];
+        for (int k = 1; k < 9; ++k) a[k] = c.sd[k] * n[k] + c.hd[k] * (D)S[k];
         // M^-1 = M^T D^-1
         const D c0 = a[0] - a[1] - D(2) * a[2];
         const D c5 = a[0] + D(2) * a[1] + a[2];
@@ -489,7 +494,7 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
                       tile[lc + W],     tile[lc - W],     tile[lc + W + 1],
                       tile[lc + W - 1], tile[lc - W - 1], tile[lc - W + 1]};
     float fs[9];
-    collide<R, D, SCHEME, COLL>(f, nb, c, fs);
+    collide<R, D, SCHEME, COLL>(f, nb, c, fs, density9<D>(f));
     stream_out<R, D>(fout, c, x, y, fs, c.flags & kFlagNT);
 }
 
@@ -540,12 +545,16 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     const int ys = dir > 0 ? y0 : y1 - 1;
     auto row = [&](int k) { return wrapy(ys + dir * k); };
     float fa[9], fb[9], fc[9], hc[9];
+    D ra = D(0), rb = D(0);  // FP64 densities of rows fa and fb, kept from their psi
     {
         const unsigned rm = fr * row(-1), r0 = fr * row(0), rp = fr * row(1);
         if (active) bload9(rin, vx, rm, qs, fc);
         if (active) bload9(rin, vx, r0, qs, fa);
         if (active) slot(-1)[tx + 1] = c.psi_of(fc);
-        if (active) slot(0)[tx + 1] = c.psi_of(fa);
+        if (active) {
+            ra = density9<D>(fa);
+            slot(0)[tx + 1] = c.psi_of_rho(ra);
+        }
         if (PF == 2 && active) bload9(rin, vx, rp, qs, fb);
         if (halo) {
             bload9(rin, vh, rm, qs, hc);
@@ -577,7 +586,10 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
                 ahead[hslot] = c.psi_of(hc);
             }
         }
-        if (active) ahead[tx + 1] = c.psi_of(fb);
+        if (active) {
+            rb = density9<D>(fb);
+            ahead[tx + 1] = c.psi_of_rho(rb);
+        }
         __syncthreads();
         if (active) {
             const float *behind = slot(k - 1), *rc = slot(k);
@@ -586,10 +598,11 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
             const Nb<float> nb = {rc[l], rc[l + 1], rc[l - 1], rn[l], rs[l],
                                   rn[l + 1], rn[l - 1], rs[l - 1], rs[l + 1]};
             float fs[9];
-            collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
+            collide<R, D, SCHEME, COLL>(fa, nb, c, fs, ra);
             bstream_out<R, D>(rout, c, x, row(k), fs, nt);
         }
         if (PF == 2 && halo && more) slot(k + 2)[hslot] = c.psi_of(hc);
+        ra = rb;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             fa[q] = fb[q];
@@ -1007,6 +1020,10 @@ __global__ void copy_tail_kernel(float *__restrict__ dst, const float *__restric
 // ---------------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------------
+// Squared norms of the rows of the D2Q9 moment matrix (rho, e, epsilon, j_x, q_x, j_y, q_y,
+// p_xx, p_xy): its rows are orthogonal, so M^-1 = M^T diag(1 / norm).
+constexpr double kRowNorm[9] = {9.0, 36.0, 36.0, 6.0, 12.0, 6.0, 12.0, 4.0, 4.0};
+
 template <typename R, typename D>
 StepConst<R, D> make_const(const Physics &p, int flags) {
     StepConst<R, D> c{};
@@ -1032,8 +1049,8 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.li = (R)(p.sigma / (p.tau - 0.5));
     c.li2 = (R)(2.0 * p.sigma);
     for (int k = 0; k < 9; ++k) {
-        c.s[k] = (D)p.s[k];
-        c.hs[k] = (D)(1.0 - p.s[k] / 2.0);
+        c.sd[k] = (D)(p.s[k] / kRowNorm[k]);
+        c.hd[k] = (D)((1.0 - p.s[k] / 2.0) / kRowNorm[k]);
         c.lim[k] = (R)(1.0 / (1.0 / p.s[k] - 0.5));
     }
     return c;
