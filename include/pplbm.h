@@ -224,8 +224,10 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_out);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around every launch of
- * the two step kernels while enabled.  lbm_timing returns the summed milliseconds of the
- * density/psi pass and of the fused pass and the number of steps timed, then resets them. */
+ * the step kernels while enabled.  lbm_timing returns the summed milliseconds of the
+ * density/psi pass and of the fused pass (with the one-pass sweep: ~0 and the sweep kernel)
+ * and the number of steps timed, then resets them.  While enabled, pending events are folded
+ * into the sums every 1024 steps (one host synchronisation), so memory stays bounded. */
 int lbm_timing_enable(lbm_t *h, int enable);
 int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps);
 
@@ -291,7 +293,7 @@ int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double 
                            double mass, double *shift_out);
 
 /* Autotuner for the batch: times trial_steps (even) steps of every lattice for strip widths
- * tx in {64, 128, 256} with and without LBM_LAUNCH_SHALLOW, then, per size class (lattices whose
+ * tx in {64, 128, 256, 512} with and without LBM_LAUNCH_SHALLOW, then, per size class (lattices whose
  * longer side rounds up to the same power of two), segment heights {8, 16, 32, 64}; keeps the
  * fastest and applies it.  Needs every lattice initialised; saves and restores the populations,
  * step counts and activity flags, so the batch resumes exactly where it was.  cache_path (may be

@@ -40,9 +40,10 @@ struct lbm {
     double *stats_partial = nullptr;
     double *stats_out = nullptr;
     bool timing = false;
-    std::vector<hipEvent_t> events;  // 3 per timed step
+    std::vector<hipEvent_t> events;  // 3 per timed step not yet folded into the sums
     size_t events_used = 0;
     long long timed_steps = 0;
+    double timed_a = 0.0, timed_b = 0.0;  // folded milliseconds (psi pass, main pass)
     std::string err;
 };
 
@@ -161,9 +162,9 @@ int maxwell(const lbm_eos &e, double *rho_g, double *rho_l) {
     return LBM_OK;
 }
 
-// One-pass sweep with strips as wide as 256 columns and segments as tall as 8 rows, two rows
-// of loads in flight and XCD-ordered tiles (the fastest measured shape on the 4096^2 MRT
-// droplet), narrowed and shortened (down to 64 x 4) until the launch has about 1024
+// One-pass sweep with strips as wide as 512 columns and segments as tall as 8 rows, two rows
+// of loads in flight and XCD-ordered tiles (the fastest measured shape on MRT droplets from
+// 2048^2 to 8192^2), narrowed and shortened (down to 64 x 4) until the launch has about 1024
 // workgroups to spread over the 256 compute units.  lbm_set_launch or lbm_autotune replaces it.
 pplbm::Launch default_launch(int nx, int ny) {
     pplbm::Launch L;
@@ -245,13 +246,35 @@ void release_buffers(lbm *h) {
 }
 
 int ensure_stats(lbm *h) {
-    if (h->stats_partial) return LBM_OK;
+    if (h->stats_partial && h->stats_out) return LBM_OK;
     const size_t n = pplbm::stats_partial_count(h->p) * pplbm::kStatsFields;
-    if (hipMalloc(&h->stats_partial, n * sizeof(double)) != hipSuccess ||
-        hipMalloc(&h->stats_out, pplbm::kStatsOut * sizeof(double)) != hipSuccess) {
+    double *part = nullptr, *out = nullptr;
+    if (hipMalloc(&part, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&out, pplbm::kStatsOut * sizeof(double)) != hipSuccess) {
+        if (part) (void)hipFree(part);
         (void)hipGetLastError();
         return fail(h, LBM_ENOMEM, "device allocation of the reduction buffers failed");
     }
+    h->stats_partial = part;
+    h->stats_out = out;
+    return LBM_OK;
+}
+
+// Timing events are folded into running sums once this many steps are pending, so a long
+// timed run holds a bounded number of events (one host synchronisation per fold).
+constexpr size_t kTimingFoldSteps = 1024;
+
+int fold_timing(lbm *h) {
+    if (h->events_used == 0) return LBM_OK;
+    HIP_TRY(h, hipEventSynchronize(h->events[h->events_used - 1]));
+    for (size_t k = 0; k + 3 <= h->events_used; k += 3) {
+        float t1 = 0, t2 = 0;
+        HIP_TRY(h, hipEventElapsedTime(&t1, h->events[k], h->events[k + 1]));
+        HIP_TRY(h, hipEventElapsedTime(&t2, h->events[k + 1], h->events[k + 2]));
+        h->timed_a += t1;
+        h->timed_b += t2;
+    }
+    h->events_used = 0;
     return LBM_OK;
 }
 
@@ -494,6 +517,10 @@ int lbm_step(lbm_t *h, int n) {
         float *fc = h->f[h->cur], *fn = h->f[1 - h->cur];
         hipEvent_t *ev = nullptr;
         if (h->timing) {
+            if (h->events_used >= 3 * kTimingFoldSteps) {
+                int rc = fold_timing(h);
+                if (rc) return rc;
+            }
             if (h->events_used + 3 > h->events.size()) {
                 for (int k = 0; k < 3 * 64; ++k) {
                     hipEvent_t e;
@@ -788,18 +815,12 @@ int lbm_timing_enable(lbm_t *h, int enable) {
 int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps) {
     if (!h) return LBM_EINVAL;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    double a = 0, b = 0;
-    for (size_t k = 0; k + 3 <= h->events_used; k += 3) {
-        float t1 = 0, t2 = 0;
-        HIP_TRY(h, hipEventElapsedTime(&t1, h->events[k], h->events[k + 1]));
-        HIP_TRY(h, hipEventElapsedTime(&t2, h->events[k + 1], h->events[k + 2]));
-        a += t1;
-        b += t2;
-    }
-    if (psi_ms) *psi_ms = a;
-    if (fused_ms) *fused_ms = b;
+    int rc = fold_timing(h);
+    if (rc) return rc;
+    if (psi_ms) *psi_ms = h->timed_a;
+    if (fused_ms) *fused_ms = h->timed_b;
     if (steps) *steps = h->timed_steps;
-    h->events_used = 0;
+    h->timed_a = h->timed_b = 0.0;
     h->timed_steps = 0;
     return LBM_OK;
 }

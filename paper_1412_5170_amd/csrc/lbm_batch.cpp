@@ -355,7 +355,8 @@ int lbm_batch_init_rest(lbm_batch_t *b, int i, const double *rho0) {
     if (rc) return rc;
     rc = rest_state(b, i);
     if (rc) b->initialised[i] = b->active[i] = 0;
-    return rc ? rc : upload_tiles(b);
+    const int up = upload_tiles(b);  // drops the lattice again if the rest state failed
+    return rc ? rc : up;
 }
 
 int lbm_batch_init_tanh(lbm_batch_t *b, int i, double R, double W, int droplet) {
@@ -550,7 +551,7 @@ int lbm_batch_autotune(lbm_batch_t *b, const char *cache_path, int trial_steps, 
     std::vector<int> best_rows = rows0;
     double best_ms = 1e300, ms = 0;
     // stage 1: strip width and prefetch depth at the current segment heights
-    for (int tx : {64, 128, 256}) {
+    for (int tx : {64, 128, 256, 512}) {
         for (int fl : {pplbm::kFlagShallow, 0}) {
             if (rc) break;
             rc = trial(tx, fl, rows0, &ms);

@@ -86,3 +86,21 @@ def test_batch_autotune_restores_state(L, tmp_path):
     for i in range(3):
         assert np.array_equal(a.populations(i), b.populations(i))
     assert make().autotune(str(cache), trial_steps=4) == -1.0
+
+
+def test_kernel_timing_folds_long_runs(L):
+    """Per-kernel timing over more steps than one fold (1024): every step is counted once, the
+    sum is positive, and reading resets it; timing does not change the state."""
+    say("[timing] 96x80, 2600 timed steps")
+    lat = _lattice(L, 96, 80)
+    ref = _lattice(L, 96, 80)
+    lat.timing_enable(True)
+    lat.timing()
+    for n in (1000, 1000, 600):
+        lat.step(n)
+    a, b, steps = lat.timing()
+    lat.timing_enable(False)
+    assert steps == 2600 and b > 0 and a >= 0
+    assert lat.timing()[2] == 0
+    ref.step(2600)
+    assert np.array_equal(lat.populations(), ref.populations())
