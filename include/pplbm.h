@@ -175,6 +175,7 @@ enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1 };
 #define LBM_LAUNCH_NONTEMPORAL 1
 #define LBM_LAUNCH_XCD_ORDER 2
 #define LBM_LAUNCH_SHALLOW 4
+#define LBM_LAUNCH_SERIAL_KINDS 8 /* batch only: see lbm_batch_set_launch */
 int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags);
 int lbm_get_launch(const lbm_t *h, int *kernel, int *tx, int *ty, int *flags);
 
@@ -250,7 +251,11 @@ void lbm_batch_destroy(lbm_batch_t *b);
 
 /* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups per kind
  * (0: one per tile up to 2048; rounded down to a multiple of 8, each XCD walking its own eighth
- * of the tile list), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW.  Default: tx = 256,
+ * of the tile list), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW |
+ * LBM_LAUNCH_SERIAL_KINDS.  The kinds (forcing scheme and collision) touch disjoint lattices,
+ * so by default the captured graph holds one independent chain of launches per kind, which the
+ * GPU may run side by side; LBM_LAUNCH_SERIAL_KINDS captures them one after another on the
+ * batch's stream instead.  Results are bitwise the same either way.  Default: tx = 256,
  * groups = 0, flags = 0 (the fastest measured on the 64-lattice droplet sweep). */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 

@@ -48,6 +48,9 @@ struct lbm_batch {
     // launch
     int tx = 256, groups = 0, flags = 0;  // 256-column strips, two rows of loads in flight
     hipStream_t stream = nullptr;
+    std::vector<hipStream_t> side;   // one more stream per kind beyond the first (capture only)
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
     bool tiles_dirty = true;
@@ -161,15 +164,60 @@ int launch_steps(lbm_batch *b, int n) {
     return LBM_OK;
 }
 
+// The same launches as launch_steps, one chain per kind on its own stream: forked from and
+// joined back into the batch's stream, so that a capture records independent branches.
+// Every launch and the joins are issued even after an error, so the capture can be closed.
+int launch_steps_by_kind(lbm_batch *b, int n) {
+    const size_t nk = b->kinds.size();
+    hipError_t e = hipEventRecord(b->fork, b->stream);
+    for (size_t j = 1; j < nk; ++j) {
+        const hipError_t w = hipStreamWaitEvent(b->side[j - 1], b->fork, 0);
+        if (e == hipSuccess) e = w;
+    }
+    for (size_t j = 0; j < nk; ++j) {
+        hipStream_t s = j == 0 ? b->stream : b->side[j - 1];
+        for (int k = 0; k < n && e == hipSuccess; ++k)
+            e = pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
+                                         b->kinds[j] % 2, k & 1, b->tx, grid_groups(b),
+                                         b->flags & pplbm::kFlagShallow, s);
+    }
+    for (size_t j = 1; j < nk; ++j) {
+        hipError_t w = hipEventRecord(b->join[j - 1], b->side[j - 1]);
+        if (w == hipSuccess) w = hipStreamWaitEvent(b->stream, b->join[j - 1], 0);
+        if (e == hipSuccess) e = w;
+    }
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int ensure_side_streams(lbm_batch *b) {
+    const size_t need = b->kinds.size() > 0 ? b->kinds.size() - 1 : 0;
+    if (!b->fork) BHIP(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    while (b->side.size() < need) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        BHIP(b, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));  // default priority
+        b->side.push_back(s);
+        BHIP(b, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->join.push_back(ev);
+    }
+    return LBM_OK;
+}
+
 int ensure_graph(lbm_batch *b, int steps) {
     if (b->graph && b->graph_steps == steps) return LBM_OK;
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    const bool by_kind = b->kinds.size() > 1 && !(b->flags & LBM_LAUNCH_SERIAL_KINDS);
+    if (by_kind) {
+        int rc = ensure_side_streams(b);
+        if (rc) return rc;
+    }
     hipGraph_t g = nullptr;
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_steps(b, steps);
+    int rc = by_kind ? launch_steps_by_kind(b, steps) : launch_steps(b, steps);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -273,6 +321,9 @@ void lbm_batch_destroy(lbm_batch_t *b) {
     for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->meta, (void *)b->sblocks,
                     (void *)b->ranges, (void *)b->ids, (void *)b->partial, (void *)b->out})
         if (p) (void)hipFree(p);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -281,8 +332,9 @@ int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags) {
     if (!b) return LBM_EINVAL;
     if (tx < 64 || tx % 64 || tx > 512 || groups < 0)
         return bfail(b, LBM_EINVAL, "tx: multiple of 64 up to 512; groups >= 0 (0 = automatic)");
-    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW))
-        return bfail(b, LBM_EINVAL, "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW");
+    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW | LBM_LAUNCH_SERIAL_KINDS))
+        return bfail(b, LBM_EINVAL,
+                     "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW, LBM_LAUNCH_SERIAL_KINDS");
     b->tx = tx;
     b->groups = groups;
     b->flags = flags;

@@ -46,18 +46,22 @@ def _single(L, m, steps, tx, rows):
     return lat.populations()
 
 
-@pytest.mark.parametrize("tx,flags", [(128, 4), (64, 0), (256, 4)])
+@pytest.mark.parametrize("tx,flags", [(128, 4), (64, 0), (256, 4), (256, 12), (128, 8)])
 def test_batch_members_match_single_lattices_bitwise(L, tx, flags):
+    """Five kinds (scheme, collision): by default one concurrent chain of launches per kind in
+    the captured graph, with LBM_LAUNCH_SERIAL_KINDS (8) one chain; the graph is replayed and
+    every replay is checked."""
     say(f"[batch bitwise] tx {tx} flags {flags}")
     b = L.Batch(MEMBERS, tx=tx, flags=flags)
     for i, m in enumerate(MEMBERS):
         b.init(i, _rho0(m))
         b.set_segment(i, 16 + 8 * i)
-    b.step(24)
-    for i, m in enumerate(MEMBERS):
-        assert b.steps(i) == 24
-        ref = _single(L, m, 24, tx, 16 + 8 * i)
-        assert np.array_equal(b.populations(i), ref), i
+    for replay in (1, 2, 3):
+        b.step(24)
+        for i, m in enumerate(MEMBERS):
+            assert b.steps(i) == 24 * replay
+            ref = _single(L, m, 24 * replay, tx, 16 + 8 * i)
+            assert np.array_equal(b.populations(i), ref), (replay, i)
 
 
 def test_batch_run_drops_converged_and_unstable(L):
