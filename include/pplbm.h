@@ -157,8 +157,7 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
  * the sweep with tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER,
- * narrowed (tx, then ty) on small lattices until the launch has about 1024 workgroups; a
- * lattice whose population buffer exceeds 4 GiB uses the two-pass kernel (256 x 4).
+ * narrowed (tx, then ty) on small lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
  *     reads it; (tx, ty) = threads per workgroup of the fused pass (tx a multiple of 64,
  *     tx * ty <= 1024).  116 bytes of memory traffic per node and step.
@@ -166,8 +165,10 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *     sweeps a strip of tx columns over segments of ty rows, computing psi from the
  *     populations as it loads them, so each population is read once: 72 bytes per node and
  *     step plus the strip and segment edges.  Addresses the populations through 32-bit
- *     buffer offsets, so 9 * 4 * pitch * ny must stay below 4 GiB (LBM_EINVAL otherwise; such
- *     lattices default to the two-pass step).  The batch's lattices obey the same limit.
+ *     buffer offsets: from the buffer's start while it is below 4 GiB, else from each row's
+ *     start (about 3 % slower), which needs LBM_LAYOUT_ROWS -- a planes-layout lattice beyond
+ *     4 GiB takes the two-pass step (LBM_EINVAL for the sweep; lbm_set_layout switches it).
+ *     The batch's lattices must stay below 4 GiB each.
  * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
  *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
  *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */

@@ -211,6 +211,13 @@ int validate(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     return LBM_OK;
 }
 
+// The sweep addresses populations with 32-bit buffer offsets: the whole buffer below 4 GiB,
+// else one resource per row, which needs the row-interleaved layout (a row's nine planes
+// within 9 x pitch floats).
+bool sweep_fits(const lbm *h) {
+    return pplbm::pop_bytes(h->p) <= pplbm::kSweepMaxBytes || h->layout == LBM_LAYOUT_ROWS;
+}
+
 int ensure_buffers(lbm *h) {
     if (h->f[0]) return LBM_OK;
     size_t fb, pb;
@@ -352,12 +359,7 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     h->p = p;
     h->xa = nx / 2;
     h->ya = ny / 2;
-    h->launch = default_launch(nx, ny);
-    if (pplbm::pop_bytes(p) > pplbm::kSweepMaxBytes) {  // beyond 32-bit buffer offsets
-        h->launch.kernel = pplbm::kKernelTwoPass;
-        h->launch.tx = 256;
-        h->launch.ty = 4;
-    }
+    h->launch = default_launch(nx, ny);  // beyond 4 GiB the sweep takes per-row resources
     *out = h;
     return LBM_OK;
 }
@@ -421,6 +423,11 @@ int lbm_set_layout(lbm_t *h, int layout) {
     h->layout = layout;
     h->p.frow = layout == LBM_LAYOUT_ROWS ? 9 * h->p.pitch : h->p.pitch;
     h->p.fq = layout == LBM_LAYOUT_ROWS ? h->p.pitch : h->p.plane;
+    if (!sweep_fits(h) && h->launch.kernel == pplbm::kKernelSweep) {
+        h->launch.kernel = pplbm::kKernelTwoPass;  // planes beyond 4 GiB: 64-bit plane offsets
+        h->launch.tx = 256;
+        h->launch.ty = 4;
+    }
     return LBM_OK;
 }
 
@@ -446,8 +453,9 @@ int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags) {
     } else if (kernel == LBM_KERNEL_SWEEP) {
         if (tx < 64 || tx % 64 || tx > 512 || ty < 1)
             return fail(h, LBM_EINVAL, "sweep: tx a multiple of 64 up to 512, ty >= 1 rows");
-        if (pplbm::pop_bytes(h->p) > pplbm::kSweepMaxBytes)
-            return fail(h, LBM_EINVAL, "sweep: population buffer beyond 4 GiB (use the two-pass step)");
+        if (!sweep_fits(h))
+            return fail(h, LBM_EINVAL,
+                        "sweep: planes layout beyond 4 GiB (use the rows layout or the two-pass step)");
     } else {
         return fail(h, LBM_EINVAL, "unknown kernel");
     }

@@ -101,7 +101,8 @@ struct StepConst {
     int nx, ny;
     size_t pitch;      // psi row stride (floats)
     size_t frow, fq;   // population row and velocity strides (floats)
-    unsigned fbytes;   // bytes of one population buffer (the one-pass sweep needs < 4 GiB)
+    unsigned fbytes;   // bytes of one population buffer when below 4 GiB (whole-buffer resource)
+    size_t ffloats;    // floats of one population buffer (per-row resources beyond 4 GiB)
     int flags;         // kFlagNT | kFlagXCD
     D bq, RT, a, K, two_over_G;  // EOS (Eq. 29-30) and Eq. 7
     int psi_kind;     // 0: psi from the C-S EOS through Eq. 7; 1: psi of Eq. 33
@@ -363,6 +364,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const float *p, unsig
                                              kBufferWord3);
 }
 
+// Lattices whose population buffer exceeds 4 GiB (32-bit offsets) get one resource per row,
+// based at the row's first float by 64-bit scalar arithmetic and bounded by the end of the
+// buffer: the velocity plane stays in the scalar offset and the column in the per-lane offset
+// (row-interleaved layout only, where a whole row spans 9 x pitch floats).  About 3 % slower
+// than the whole-buffer resource (more scalar registers), so it is kept for those lattices.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *p, size_t frow,
+                                                           size_t total, int row) {
+    const size_t off = (size_t)row * frow;
+    const size_t rem = (total - off) * sizeof(float);
+    const unsigned bytes = rem > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)rem;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p + off), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+
 __device__ __forceinline__ void bload9(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                        unsigned qstride, float v[9]) {
 #pragma unroll
@@ -376,6 +391,34 @@ __device__ __forceinline__ void bput(__amdgpu_buffer_rsrc_t r, float v, unsigned
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 2);  // nt
     else
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Push streaming (Eq. 36) through the per-row resources of rows y, y + 1 and y - 1.
+template <typename R, typename D>
+__device__ __forceinline__ void bstream_out_rows(float *fout, const StepConst<R, D> &c, int x,
+                                                 int y, const float fs[9], bool nt) {
+    const unsigned vx = 4u * x, ve = 4u * (x + 1 == c.nx ? 0 : x + 1),
+                   vw = 4u * (x == 0 ? c.nx - 1 : x - 1);
+    const int yn = y + 1 == c.ny ? 0 : y + 1, ys = y == 0 ? c.ny - 1 : y - 1;
+    const unsigned q = 4u * (unsigned)c.fq;
+    const __amdgpu_buffer_rsrc_t rc = row_rsrc(fout, c.frow, c.ffloats, y),
+                                 rn = row_rsrc(fout, c.frow, c.ffloats, yn),
+                                 rs = row_rsrc(fout, c.frow, c.ffloats, ys);
+    auto all = [&](auto put1) {
+        put1(rc, fs[0], vx, 0);
+        put1(rc, fs[1], ve, q);
+        put1(rn, fs[2], vx, 2 * q);
+        put1(rc, fs[3], vw, 3 * q);
+        put1(rs, fs[4], vx, 4 * q);
+        put1(rn, fs[5], ve, 5 * q);
+        put1(rn, fs[6], vw, 6 * q);
+        put1(rs, fs[7], vw, 7 * q);
+        put1(rs, fs[8], ve, 8 * q);
+    };
+    if (nt)
+        all([&](__amdgpu_buffer_rsrc_t r, float v, unsigned vo, unsigned so) { bput(r, v, vo, so, true); });
+    else
+        all([&](__amdgpu_buffer_rsrc_t r, float v, unsigned vo, unsigned so) { bput(r, v, vo, so, false); });
 }
 
 // Push streaming (Eq. 36) through the buffer resource.
@@ -510,7 +553,7 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
 // ---------------------------------------------------------------------------------------
 // One tile of the sweep: columns [x0, x0 + blockDim.x) (clipped at nx) and rows [y0, y0 + H)
 // (clipped at ny) of the lattice described by c; ring is the workgroup's LDS (4 x (TX + 2)).
-template <typename R, typename D, int SCHEME, int COLL, int PF>
+template <typename R, typename D, int SCHEME, int COLL, int PF, bool BIG = false>
 __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float *__restrict__ fout,
                                            const StepConst<R, D> &c, int x0, int y0, int H,
                                            float *ring) {
@@ -525,8 +568,11 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     const int hcol = tx == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + na == nx ? 0 : x0 + na);
     const int hslot = tx == 0 ? 0 : na + 1;
     const bool nt = c.flags & kFlagNT;
-    const __amdgpu_buffer_rsrc_t rin = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
+    const __amdgpu_buffer_rsrc_t rbuf = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
     const unsigned qs = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
+    // Loads of row r: resource and scalar offset (whole buffer, or the row's own resource).
+    auto rin = [&](int r) { return BIG ? row_rsrc(fin, c.frow, c.ffloats, r) : rbuf; };
+    auto roff = [&](int r) { return BIG ? 0u : fr * (unsigned)r; };
     const unsigned vx = 4u * x, vh = 4u * hcol;
     auto wrapy = [&](int yy) { return yy >= ny ? yy - ny : (yy < 0 ? yy + ny : yy); };
     auto slot = [&](int yy_rel) { return ring + ((yy_rel + 1) & 3) * W; };
@@ -547,22 +593,22 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     float fa[9], fb[9], fc[9], hc[9];
     D ra = D(0), rb = D(0);  // FP64 densities of rows fa and fb, kept from their psi
     {
-        const unsigned rm = fr * row(-1), r0 = fr * row(0), rp = fr * row(1);
-        if (active) bload9(rin, vx, rm, qs, fc);
-        if (active) bload9(rin, vx, r0, qs, fa);
+        const int rm = row(-1), r0 = row(0), rp = row(1);
+        if (active) bload9(rin(rm), vx, roff(rm), qs, fc);
+        if (active) bload9(rin(r0), vx, roff(r0), qs, fa);
         if (active) slot(-1)[tx + 1] = c.psi_of(fc);
         if (active) {
             ra = density9<D>(fa);
             slot(0)[tx + 1] = c.psi_of_rho(ra);
         }
-        if (PF == 2 && active) bload9(rin, vx, rp, qs, fb);
+        if (PF == 2 && active) bload9(rin(rp), vx, roff(rp), qs, fb);
         if (halo) {
-            bload9(rin, vh, rm, qs, hc);
+            bload9(rin(rm), vh, roff(rm), qs, hc);
             slot(-1)[hslot] = c.psi_of(hc);
-            bload9(rin, vh, r0, qs, hc);
+            bload9(rin(r0), vh, roff(r0), qs, hc);
             slot(0)[hslot] = c.psi_of(hc);
             if (PF == 2) {
-                bload9(rin, vh, rp, qs, hc);
+                bload9(rin(rp), vh, roff(rp), qs, hc);
                 slot(1)[hslot] = c.psi_of(hc);
             }
         }
@@ -574,15 +620,17 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
             // Row k+2 is needed only while row k+1 is still inside the segment.
             more = k + 2 <= nrow;
             if (more) {
-                const unsigned r2 = fr * row(k + 2);
-                if (active) bload9(rin, vx, r2, qs, fc);
-                if (halo) bload9(rin, vh, r2, qs, hc);
+                const int r2 = row(k + 2);
+                const __amdgpu_buffer_rsrc_t rr = rin(r2);
+                if (active) bload9(rr, vx, roff(r2), qs, fc);
+                if (halo) bload9(rr, vh, roff(r2), qs, hc);
             }
         } else {
-            const unsigned r1 = fr * row(k + 1);
-            if (active) bload9(rin, vx, r1, qs, fb);
+            const int r1 = row(k + 1);
+            const __amdgpu_buffer_rsrc_t rr = rin(r1);
+            if (active) bload9(rr, vx, roff(r1), qs, fb);
             if (halo) {
-                bload9(rin, vh, r1, qs, hc);
+                bload9(rr, vh, roff(r1), qs, hc);
                 ahead[hslot] = c.psi_of(hc);
             }
         }
@@ -599,7 +647,10 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
                                   rn[l + 1], rn[l - 1], rs[l - 1], rs[l + 1]};
             float fs[9];
             collide<R, D, SCHEME, COLL>(fa, nb, c, fs, ra);
-            bstream_out<R, D>(rout, c, x, row(k), fs, nt);
+            if constexpr (BIG)
+                bstream_out_rows<R, D>(fout, c, x, row(k), fs, nt);
+            else
+                bstream_out<R, D>(rout, c, x, row(k), fs, nt);
         }
         if (PF == 2 && halo && more) slot(k + 2)[hslot] = c.psi_of(hc);
         ra = rb;
@@ -611,29 +662,29 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     }
 }
 
-template <typename R, typename D, int SCHEME, int COLL, int PF>
+template <typename R, typename D, int SCHEME, int COLL, int PF, bool BIG>
 __device__ __forceinline__ void sweep_entry(const float *__restrict__ fin, float *__restrict__ fout,
                                             const StepConst<R, D> &c, int H) {
     extern __shared__ float ring[];  // 4 rows x (TX + 2)
     const int b = tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y,
                           c.flags & kFlagXCD);
-    sweep_tile<R, D, SCHEME, COLL, PF>(fin, fout, c, (b % gridDim.x) * blockDim.x,
-                                       (b / gridDim.x) * H, H, ring);
+    sweep_tile<R, D, SCHEME, COLL, PF, BIG>(fin, fout, c, (b % gridDim.x) * blockDim.x,
+                                            (b / gridDim.x) * H, H, ring);
 }
 
-template <typename R, typename D, int SCHEME, int COLL, int PF>
+template <typename R, typename D, int SCHEME, int COLL, int PF, bool BIG = false>
 __global__ void __launch_bounds__(512) sweep_kernel(const float *__restrict__ fin,
                                                     float *__restrict__ fout,
                                                     StepConst<R, D> c, int H) {
-    sweep_entry<R, D, SCHEME, COLL, PF>(fin, fout, c, H);
+    sweep_entry<R, D, SCHEME, COLL, PF, BIG>(fin, fout, c, H);
 }
 
 // The same kernel asking the register allocator for five waves per SIMD: the mixed-precision
 // and FP32 variants fit without spilling (the FP64 ones would spill, so they use the plain one).
-template <typename R, typename D, int SCHEME, int COLL, int PF>
+template <typename R, typename D, int SCHEME, int COLL, int PF, bool BIG = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5, 8)))
 sweep_kernel_w5(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H) {
-    sweep_entry<R, D, SCHEME, COLL, PF>(fin, fout, c, H);
+    sweep_entry<R, D, SCHEME, COLL, PF, BIG>(fin, fout, c, H);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1032,7 +1083,8 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.pitch = p.pitch;
     c.frow = p.frow;
     c.fq = p.fq;
-    c.fbytes = (unsigned)pop_bytes(p);
+    c.fbytes = (unsigned)(pop_bytes(p) > kSweepMaxBytes ? kSweepMaxBytes : pop_bytes(p));
+    c.ffloats = pop_bytes(p) / sizeof(float);
     c.flags = flags;
     c.bq = (D)p.b_quarter;
     c.RT = (D)p.RT;
@@ -1083,6 +1135,8 @@ dim3 row_grid(int nx, int ny, int block) {
 #define PPLBM_NOEXTRA
 #define PPLBM_PF1 , 1
 #define PPLBM_PF2 , 2
+#define PPLBM_PF1_BIG , 1, true
+#define PPLBM_PF2_BIG , 2, true
 #define PPLBM_DISPATCH(KERNEL, R, D, p, grid, block, lds, s, ...) \
     PPLBM_DISPATCH_X(KERNEL, R, D, PPLBM_NOEXTRA, p, grid, block, lds, s, __VA_ARGS__)
 
@@ -1111,6 +1165,21 @@ hipError_t sweep_dispatch(const Physics &p, const Launch &L, const float *fin, f
     const StepConst<R, D> c = make_const<R, D>(p, L.flags);
     const dim3 grid((unsigned)((p.nx + L.tx - 1) / L.tx), (unsigned)((p.ny + L.ty - 1) / L.ty));
     const size_t lds = 4 * (size_t)(L.tx + 2) * sizeof(float);
+    if (pop_bytes(p) > kSweepMaxBytes) {  // per-row resources (row-interleaved layout only)
+        if (p.fq != p.pitch) return hipErrorInvalidValue;
+        if constexpr (sizeof(R) == 8) {
+            if (L.flags & kFlagShallow)
+                PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF1_BIG, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+            else
+                PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF2_BIG, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+        } else {
+            if (L.flags & kFlagShallow)
+                PPLBM_DISPATCH_X(sweep_kernel_w5, R, D, PPLBM_PF1_BIG, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+            else
+                PPLBM_DISPATCH_X(sweep_kernel_w5, R, D, PPLBM_PF2_BIG, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);
+        }
+        return hipGetLastError();
+    }
     if constexpr (sizeof(R) == 8) {
         if (L.flags & kFlagShallow)
             PPLBM_DISPATCH_X(sweep_kernel, R, D, PPLBM_PF1, p, grid, dim3(L.tx), lds, s, fin, fout, c, L.ty);

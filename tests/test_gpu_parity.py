@@ -282,3 +282,59 @@ def test_full_size_4096_sampled_windows(L):
         vref = max(vref, np.abs(vx_o).max(), np.abs(vy_o).max())
     say(f"    all windows: rho {e_rho:.3e}  v {dv / vref:.3e}")
     assert e_rho < TOL and dv / vref < TOL
+
+
+def test_sweep_beyond_4gib_rows(L):
+    """A lattice whose population buffer exceeds 4 GiB (10944 x 10944: 4.31 GB per buffer)
+    runs the sweep with one buffer resource per row.  Its state after 20 steps must equal,
+    bit for bit, the two-pass step's (64-bit pointers), and match the oracle on windows that
+    lie beyond the first 4 GiB (rows above 10901), across the periodic wrap and at the
+    interface of a droplet centred near the last row."""
+    import torch
+    n, K, win = 10944, 20, 16
+    wl = workload("droplet_4096_mrt", nx=n, ny=n)
+    margin = 2 * K + 1
+    g, l, _ = TH.maxwell(wl["T_over_Tc"])
+    cx, cy, R = n // 2 + 1234, n - 30, 150
+    rho0 = np.roll(np.roll(inputs.droplet(n, n, float(R), 5.0, l, g), cy - n // 2, axis=0),
+                   cx - n // 2, axis=1)
+    say(f"[parity > 4 GiB] {n}x{n} sweep vs two-pass, {K} steps")
+    lats = []
+    for kernel in ("sweep", "two_pass"):
+        lat = gpu_lattice(L, wl, PRECISIONS["mixed"])
+        if kernel == "two_pass":
+            lat.set_launch(L.LBM_KERNEL_TWO_PASS, 256, 4, L.LBM_LAUNCH_XCD_ORDER)
+        assert lat.get_launch()[0] == (L.LBM_KERNEL_SWEEP if kernel == "sweep"
+                                       else L.LBM_KERNEL_TWO_PASS)
+        lat.init(rho0)
+        lat.step(K)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    assert lats[0].f_a.numel() * 4 > 2 ** 32
+    assert torch.equal(lats[0].f_a, lats[1].f_a)
+    say("    sweep == two-pass bitwise")
+    lats[1] = None
+    rho_g, u_g = lats[0].read()
+    starts = [(cx + R - win // 2, cy - win // 2), (cx - R - win // 2, cy - win // 2),
+              (cx - win // 2, (cy + R) % n - win // 2), (cx - win // 2, cy - R - win // 2),
+              (cx + 106 - win // 2, (cy + 106) % n - win // 2),
+              (cx + 147 - win // 2, n - win // 2)]                  # interface across the wrap
+    e_rho, dv, vref = 0.0, 0.0, 0.0
+    for x0, y0 in starts:
+        m = win + 2 * margin
+        xs = np.arange(x0 - margin, x0 - margin + m) % n
+        ys = np.arange(y0 - margin, y0 - margin + m) % n
+        P = rho0[np.ix_(ys, xs)]
+        Q = np.block([[P, P[:, ::-1]], [P[::-1, :], P[::-1, ::-1]]])
+        p = oracle_params(dict(wl, nx=2 * m, ny=2 * m))
+        fl = O.fields(p, O.step(p, O.init_feq(Q), K))
+        inner = np.s_[margin:margin + win, margin:margin + win]
+        wy, wx = np.ix_(ys[margin:margin + win], xs[margin:margin + win])
+        e = float(np.max(np.abs(rho_g[wy, wx] - fl["rho"][inner]) / fl["rho"][inner]))
+        d = max(np.abs(u_g[wy, wx, 0] - fl["vx"][inner]).max(),
+                np.abs(u_g[wy, wx, 1] - fl["vy"][inner]).max())
+        say(f"    window at ({x0 % n}, {y0 % n}): rho {e:.3e}  |dv| {d:.3e}")
+        e_rho, dv = max(e_rho, e), max(dv, d)
+        vref = max(vref, np.abs(fl["vx"][inner]).max(), np.abs(fl["vy"][inner]).max())
+    say(f"    all windows: rho {e_rho:.3e}  v {dv / vref:.3e}")
+    assert e_rho < TOL and dv / vref < TOL
