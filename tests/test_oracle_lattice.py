@@ -41,6 +41,18 @@ def test_mrt_matrix_is_orthogonal_and_inverse_is_exact(oracle):
     assert m[5] == pytest.approx(0.4 * -0.02)
 
 
+def test_equilibrium_moments_closed_form(oracle):
+    """Every row of m_eq = M f^eq(rho, v) (Eq. 34 with Eq. 2) against the closed form
+    rho (1, -2 + 3 v.v, 1 - 3 v.v, v_x, -v_x, v_y, -v_y, v_x^2 - v_y^2, v_x v_y) that the
+    kernels evaluate: a wrong or misordered row of M, or a wrong f^eq weight, fails here."""
+    M, _ = oracle.mrt_matrix()
+    for rho, vx, vy in [(0.4, 0.03, -0.02), (0.002, -0.11, 0.07), (1.3, 0.0, 0.2)]:
+        v2 = vx * vx + vy * vy
+        want = rho * np.array([1, -2 + 3 * v2, 1 - 3 * v2, vx, -vx, vy, -vy, vx * vx - vy * vy,
+                               vx * vy])
+        assert np.allclose(M @ oracle.feq(rho, vx, vy), want, rtol=0, atol=1e-15 * max(rho, 1))
+
+
 def _sinusoid(nx, ny, axis, rho0=0.2, amp=0.02, k=1):
     y, x = np.mgrid[0:ny, 0:nx]
     coord = {"x": x / nx, "y": y / ny, "xy": ((x + y) % nx) / nx}[axis]
