@@ -217,7 +217,6 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
     const D inv = recip<D>(rho_d), hinv = D(0.5) * inv;
     const D uxd = jx * inv, uyd = jy * inv;
     const D vxd = uxd + Fxd * hinv, vyd = uyd + Fyd * hinv;
-    const R rho = (R)rho_d;
     const R ux = (R)uxd, uy = (R)uyd;
     const R vx = (R)vxd, vy = (R)vyd;
     const R Fx = (R)Fxd, Fy = (R)Fyd;
