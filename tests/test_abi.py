@@ -164,3 +164,46 @@ def test_load_rejects_missing_and_foreign_files(tmp_path):
         assert lbm.lbm_load(h, os.fsencode(str(bad))) == lbm.LBM_EINVAL
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_launch_rules_beyond_4gib():
+    """Host-side launch rules (no GPU call is made): a lattice above 4 GiB per population
+    buffer keeps the one-pass sweep in the rows layout (per-row buffer resources); switching it
+    to the planes layout moves it to the two-pass step, and the sweep is then refused.  The
+    default shape is 512 x 8 with two rows in flight and XCD order; small lattices narrow it."""
+    from paper_1412_5170_amd import lbm
+    eos, frc, coll = lbm.make_eos(0.5, K=1 / 49), lbm.make_force("GUO_LI", sigma=0.125), \
+        lbm.make_collision("MRT")
+
+    def create(nx, ny):
+        h = lbm._P()
+        assert lbm.lbm_create(nx, ny, ctypes.byref(eos), ctypes.byref(frc), ctypes.byref(coll),
+                              1.0, ctypes.byref(h)) == lbm.LBM_OK
+        return h
+
+    def launch(h):
+        v = [ctypes.c_int() for _ in range(4)]
+        assert lbm.lbm_get_launch(h, *[ctypes.byref(x) for x in v]) == lbm.LBM_OK
+        return tuple(x.value for x in v)
+
+    big = create(10944, 10944)  # 9 x 4 x 10944^2 B = 4.31 GB per buffer
+    fb = ctypes.c_size_t()
+    assert lbm.lbm_layout(big, None, None, ctypes.byref(fb), None) == lbm.LBM_OK
+    assert fb.value > 2 ** 32
+    assert launch(big) == (lbm.LBM_KERNEL_SWEEP, 512, 8, lbm.LBM_LAUNCH_XCD_ORDER)
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 256, 16, 0) == lbm.LBM_OK
+    assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
+    assert launch(big)[0] == lbm.LBM_KERNEL_TWO_PASS
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 512, 8, 0) == lbm.LBM_EINVAL
+    assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_ROWS) == lbm.LBM_OK
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 512, 8, 0) == lbm.LBM_OK
+    lbm.lbm_destroy(big)
+    small = create(4096, 4096)
+    assert lbm.lbm_set_layout(small, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP, 512, 8, lbm.LBM_LAUNCH_XCD_ORDER)
+    lbm.lbm_destroy(small)
+    tiny = create(300, 130)
+    k, tx, ty, _ = launch(tiny)
+    assert k == lbm.LBM_KERNEL_SWEEP and tx <= 512 and ty <= 8
+    assert ((300 + tx - 1) // tx) * ((130 + ty - 1) // ty) >= 64
+    lbm.lbm_destroy(tiny)
