@@ -66,8 +66,10 @@ def equilibria(lbm, members, tol, check_every=500, max_steps=400_000, batch_size
         idx = order[c:c + batch_size]
         ms = [members[i] for i in idx]
         dens = [sweep.tanh_density(lbm, m) for m in ms]
-        wall, st, stat, b = sweep.run_batch(lbm, ms, dens, tol=tol, check_every=check_every,
-                                            max_steps=max_steps, tol_rho=tol_rho)
+        wall, st, stat, b = sweep.run_batch(
+            lbm, ms, dens, tol=tol, check_every=check_every, max_steps=max_steps,
+            tol_rho=tol_rho, chunk=20_000,
+            report=lambda t, c=c: say(f"warmstart: equilibria from {c}: {t}"))
         for j, i in enumerate(idx):
             steps[i], status[i] = st[j], stat[j]
             if stat[j] == 0:
@@ -294,6 +296,8 @@ def main(argv=None):
     ap.add_argument("--train-tol-rho", type=float, default=1e-8)
     ap.add_argument("--train-levels", type=int, default=19, help="sizes 96 + 16 k, k < levels")
     ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--train-large-count", type=int, default=0,
+                    help="extra training droplets of sizes 512 + 16 k, k < 33 (the sweep's largest)")
     ap.add_argument("--eval-seed", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=64)
     ap.add_argument("--eval-levels", type=int, default=57, help="sizes 128 + 16 k, k < levels")
@@ -319,22 +323,27 @@ def main(argv=None):
         sur.mean, sur.std = d["mean"], d["std"]
         out["training"] = {"loaded": a.load_net}
     else:
+        sets, out["generation"] = [], []
         if a.data:
             d = np.load(a.data)
-            X, Y = d["X"], d["Y"]
-        else:
-            tr = draw_training(1, a.train_count, n_levels=a.train_levels)
+            sets.append((d["X"], d["Y"]))
+        draws = [] if a.data else [draw_training(1, a.train_count, n_levels=a.train_levels)]
+        if a.train_large_count > 0:
+            draws.append(draw_training(2, a.train_large_count, n_min=512, n_levels=33))
+        for tr in draws:
             t0 = time.perf_counter()
             prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
             ok = status == 0
-            X = np.stack([features(m) for m in tr])[ok]
-            Y = prof[ok]
-            out["generation"] = {"members": len(tr), "converged": int(ok.sum()),
-                                 "wall_s": round(time.perf_counter() - t0, 1),
-                                 "tol": a.train_tol, "lattice_updates": int(sum(
-                                     m["nx"] * m["ny"] * st for m, st in zip(tr, steps)))}
-            if a.out:
-                np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
+            sets.append((np.stack([features(m) for m in tr])[ok], prof[ok]))
+            out["generation"].append({"members": len(tr), "converged": int(ok.sum()),
+                                      "sizes": [min(m["nx"] for m in tr), max(m["nx"] for m in tr)],
+                                      "wall_s": round(time.perf_counter() - t0, 1),
+                                      "tol": a.train_tol, "lattice_updates": int(sum(
+                                          m["nx"] * m["ny"] * st for m, st in zip(tr, steps)))})
+        X = np.concatenate([x for x, _ in sets])
+        Y = np.concatenate([y for _, y in sets])
+        if a.out and draws:
+            np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
         t0 = time.perf_counter()
         out["training"] = sur.fit(X, Y, steps=a.train_steps)
         out["training"]["wall_s"] = round(time.perf_counter() - t0, 1)
