@@ -114,8 +114,9 @@ hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblock
                               const int2 *ranges, const int *ids, int nlat, int parity, int track,
                               double *partial, double *out, hipStream_t stream);
 
-// Bytes of one population buffer (9 velocity planes).  The one-pass sweep addresses it
-// through 32-bit buffer offsets, so it needs this below 4 GiB.
+// Bytes of one population buffer (9 velocity planes).  Up to kSweepMaxBytes the one-pass
+// sweep addresses it through one buffer resource with 32-bit offsets; beyond, through one
+// resource per row (rows layout only).  The batch's lattices stay below it.
 inline size_t pop_bytes(const Physics &p) { return 9 * p.plane * sizeof(float); }
 constexpr size_t kSweepMaxBytes = 0xFFFFFFFFull;
 
