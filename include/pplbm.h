@@ -225,11 +225,13 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
  * NULL): the best time per step in ms.  Needs lbm_init first.  Synchronises. */
 int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_out);
 
-/* Per-kernel timing with HIP events recorded on the handle's stream around every launch of
- * the step kernels while enabled.  lbm_timing returns the summed milliseconds of the
- * density/psi pass and of the fused pass (with the one-pass sweep: ~0 and the sweep kernel)
- * and the number of steps timed, then resets them.  While enabled, pending events are folded
- * into the sums every 1024 steps (one host synchronisation), so memory stays bounded. */
+/* Kernel timing with HIP events recorded on the handle's stream while enabled: the two-pass
+ * step around each of its two launches, every step; the one-pass sweep around each lbm_step
+ * call's n back-to-back launches (an event between launches would cost ~5 % of the step).
+ * lbm_timing returns the summed milliseconds of the density/psi pass and of the fused pass
+ * (with the sweep: ~0 and the sweep kernels) and the number of steps timed, then resets them.
+ * While enabled, pending events are folded into the sums every 1024 timed calls or steps (one
+ * host synchronisation), so memory stays bounded. */
 int lbm_timing_enable(lbm_t *h, int enable);
 int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps);
 

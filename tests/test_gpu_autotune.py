@@ -89,18 +89,24 @@ def test_batch_autotune_restores_state(L, tmp_path):
 
 
 def test_kernel_timing_folds_long_runs(L):
-    """Per-kernel timing over more steps than one fold (1024): every step is counted once, the
-    sum is positive, and reading resets it; timing does not change the state."""
-    say("[timing] 96x80, 2600 timed steps")
+    """Kernel timing over more timed units than one fold (1024): the sweep is timed per
+    lbm_step call (1100 calls of 2 steps), the two-pass step per step (1100 steps); every step
+    is counted once, the sums are positive, reading resets them, and timing does not change
+    the state."""
+    say("[timing] 96x80, 1100 sweep calls of 2 steps, 1100 two-pass steps")
     lat = _lattice(L, 96, 80)
     ref = _lattice(L, 96, 80)
     lat.timing_enable(True)
     lat.timing()
-    for n in (1000, 1000, 600):
-        lat.step(n)
+    for _ in range(1100):
+        lat.step(2)
     a, b, steps = lat.timing()
-    lat.timing_enable(False)
-    assert steps == 2600 and b > 0 and a >= 0
+    assert steps == 2200 and b > 0 and a >= 0
     assert lat.timing()[2] == 0
-    ref.step(2600)
+    lat.set_launch(L.LBM_KERNEL_TWO_PASS, 128, 2, L.LBM_LAUNCH_XCD_ORDER)
+    lat.step(1100)
+    a2, b2, steps2 = lat.timing()
+    lat.timing_enable(False)
+    assert steps2 == 1100 and a2 > 0 and b2 > 0
+    ref.step(3300)
     assert np.array_equal(lat.populations(), ref.populations())
