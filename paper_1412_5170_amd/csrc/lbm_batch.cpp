@@ -70,6 +70,16 @@ int bfail(lbm_batch *b, int code, const std::string &m) {
         if (e_ != hipSuccess) return bfail(b, LBM_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Destroys the captured graph once no launch of it can still be running: a graph whose kinds
+// run as branches executes across streams of the runtime, and freeing it while a replay is in
+// flight (the autotuner alternates graphs of 2 and trial_steps steps back to back) is unsafe.
+void drop_graph(lbm_batch *b) {
+    if (!b->graph) return;
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+}
+
 constexpr int kAutoRowsMax = 32, kAutoRowsMin = 4;
 constexpr size_t kAutoTiles = 4096;  // ~16 workgroups per compute unit
 
@@ -103,17 +113,15 @@ int upload_tiles(lbm_batch *b) {
     size_t need = 0;
     for (int i = 0; i < b->count; ++i) need += tiles_max(b, i);
     if (need > b->max_tiles) {
+        drop_graph(b);  // the captured graph holds the old tile list pointer; let it finish
         if (b->tiles) (void)hipFree(b->tiles);
         b->tiles = nullptr;
+        b->max_tiles = 0;
         if (hipMalloc(&b->tiles, need * sizeof(int4)) != hipSuccess) {
             (void)hipGetLastError();
             return bfail(b, LBM_ENOMEM, "tile list allocation failed");
         }
         b->max_tiles = need;
-        if (b->graph) {  // the captured graph holds the old tile list pointer
-            (void)hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
-        }
     }
     b->auto_rows = kAutoRowsMax;
     for (;;) {
@@ -206,10 +214,7 @@ int ensure_side_streams(lbm_batch *b) {
 
 int ensure_graph(lbm_batch *b, int steps) {
     if (b->graph && b->graph_steps == steps) return LBM_OK;
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    drop_graph(b);
     const bool by_kind = b->kinds.size() > 1 && !(b->flags & LBM_LAUNCH_SERIAL_KINDS);
     if (by_kind) {
         int rc = ensure_side_streams(b);
@@ -335,13 +340,10 @@ int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags) {
     if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW | LBM_LAUNCH_SERIAL_KINDS))
         return bfail(b, LBM_EINVAL,
                      "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW, LBM_LAUNCH_SERIAL_KINDS");
+    drop_graph(b);
     b->tx = tx;
     b->groups = groups;
     b->flags = flags;
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
     int rc = upload_desc(b);
     return rc ? rc : upload_tiles(b);
 }
