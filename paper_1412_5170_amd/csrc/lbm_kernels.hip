@@ -688,9 +688,9 @@ sweep_kernel_w5(const float *__restrict__ fin, float *__restrict__ fout, StepCon
 
 // ---------------------------------------------------------------------------------------
 // Batched sweep: many independent lattices (own size, physics and relaxation) advanced by one
-// launch per step.  Each workgroup walks the shared tile list (lattice, x0, y0, rows) with a
-// stride of the grid size; the list and its length live in device memory, so the host can
-// drop converged lattices between replays of a captured graph.  Mixed precision.
+// launch per kind of lattice and step.  Each workgroup walks its kind's slice of the shared
+// tile list (lattice, x0, y0, rows); the list and the slices live in device memory, so the
+// host can drop converged lattices between replays of a captured graph.  Mixed precision.
 // ---------------------------------------------------------------------------------------
 struct BatchLattice {
     StepConst<float, double> c;
