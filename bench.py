@@ -178,8 +178,8 @@ def copy_probe(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not code)", file=sys.stderr)
+        print(f"bench.py: pplbm runs on one GPU; --gpus {args.gpus} is not supported (the "
+              "y-slab decomposition across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args)
