@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="droplet_4096_mrt")
     ap.add_argument("--precision", default="mixed", choices=["f32", "f64", "mixed"])
-    ap.add_argument("--kernel", default="sweep", choices=["sweep", "two_pass"])
+    ap.add_argument("--kernel", default="sweep", choices=["sweep", "sweep2", "two_pass"])
     ap.add_argument("--autotune", action="store_true",
                     help="pick the sweep's launch with the library's autotuner first")
     ap.add_argument("--launch", default=None,
@@ -119,12 +119,14 @@ def make_lattice(lbm, wl, args, kernel):
     k, tx, ty, fl = lat.get_launch()
     if kernel == "two_pass":
         k, tx, ty, fl = lbm.LBM_KERNEL_TWO_PASS, 128, 8, lbm.LBM_LAUNCH_XCD_ORDER
+    if kernel == "sweep2":
+        k, tx, ty, fl = lbm.LBM_KERNEL_SWEEP2, 256, 32, 0
     if args.launch and kernel == args.kernel:
         v = [int(t) for t in args.launch.split(",")]
         tx, ty = v[0], v[1]
         fl = v[2] if len(v) > 2 else fl
-    lat.set_launch(lbm.LBM_KERNEL_SWEEP if kernel == "sweep" else lbm.LBM_KERNEL_TWO_PASS,
-                   tx, ty, fl)
+    lat.set_launch({"sweep": lbm.LBM_KERNEL_SWEEP, "sweep2": lbm.LBM_KERNEL_SWEEP2,
+                    "two_pass": lbm.LBM_KERNEL_TWO_PASS}[kernel], tx, ty, fl)
     return lat
 
 
@@ -216,13 +218,16 @@ def main():
 
     def roofline(kernel, ev, launch):
         psi_ms, main_ms, nt = ev
-        avg = main_ms / 1e3 / nt
-        per_node = SWEEP_BYTES_PER_NODE if kernel == "sweep" else FUSED_BYTES_PER_NODE
+        steps_per_launch = 2 if kernel == "sweep2" else 1  # the two-step sweep: 2 per launch
+        avg = main_ms / 1e3 / (nt / steps_per_launch)     # per launch of the main kernel
+        per_node = FUSED_BYTES_PER_NODE if kernel == "two_pass" else SWEEP_BYTES_PER_NODE
         achieved = per_node * nodes / avg / 1e9
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-             "kernel": "sweep_kernel" if kernel == "sweep" else "fused_kernel",
-             "bytes_per_node": per_node, "avg_us": round(avg * 1e6, 2)}
+             "kernel": {"sweep": "sweep_kernel", "sweep2": "sweep2_kernel",
+                        "two_pass": "fused_kernel"}[kernel],
+             "bytes_per_node": per_node, "steps_per_launch": steps_per_launch,
+             "avg_us": round(avg * 1e6, 2)}
         if kernel == "two_pass":
             pavg = psi_ms / 1e3 / nt
             r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),

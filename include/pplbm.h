@@ -169,10 +169,17 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *     start (about 3 % slower), which needs LBM_LAYOUT_ROWS -- a planes-layout lattice beyond
  *     4 GiB takes the two-pass step (LBM_EINVAL for the sweep; lbm_set_layout switches it).
  *     The batch's lattices must stay below 4 GiB each.
+ *   LBM_KERNEL_SWEEP2: two time steps per launch (temporal blocking): each 64-lane wave sweeps
+ *     a strip of 60 output columns over segments of ty rows, computing step t on its 64
+ *     columns and step t+1 two rows behind; lanes exchange x-neighbours by DPP shifts, so no
+ *     LDS or barrier is used, and only step t+1 is written: 72 bytes per node per two steps
+ *     plus the strip and segment overlaps.  tx = threads per workgroup (independent waves,
+ *     multiple of 64, <= 256).  An odd last step of lbm_step runs the one-step sweep.  Below
+ *     4 GiB of populations only.
  * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
  *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
  *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */
-enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1 };
+enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1, LBM_KERNEL_SWEEP2 = 2 };
 #define LBM_LAUNCH_NONTEMPORAL 1
 #define LBM_LAUNCH_XCD_ORDER 2
 #define LBM_LAUNCH_SHALLOW 4

@@ -450,6 +450,11 @@ int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags) {
     if (kernel == LBM_KERNEL_TWO_PASS) {
         if (tx < 64 || tx % 64 || ty < 1 || tx * ty > 1024)
             return fail(h, LBM_EINVAL, "two-pass tile: tx a multiple of 64, ty >= 1, tx * ty <= 1024");
+    } else if (kernel == LBM_KERNEL_SWEEP2) {
+        if (tx < 64 || tx % 64 || tx > 256 || ty < 1)
+            return fail(h, LBM_EINVAL, "two-step sweep: tx a multiple of 64 up to 256, ty >= 1 rows");
+        if (pplbm::pop_bytes(h->p) > pplbm::kSweepMaxBytes)
+            return fail(h, LBM_EINVAL, "two-step sweep: population buffer beyond 4 GiB");
     } else if (kernel == LBM_KERNEL_SWEEP) {
         if (tx < 64 || tx % 64 || tx > 512 || ty < 1)
             return fail(h, LBM_EINVAL, "sweep: tx a multiple of 64 up to 512, ty >= 1 rows");
@@ -539,7 +544,8 @@ int next_events(lbm *h, hipEvent_t **ev) {
 int lbm_step(lbm_t *h, int n) {
     if (!h || n < 0) return LBM_EINVAL;
     if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_step before lbm_init");
-    const bool sweep = h->launch.kernel == pplbm::kKernelSweep;
+    const bool sweep2 = h->launch.kernel == pplbm::kKernelSweep2;
+    const bool sweep = h->launch.kernel == pplbm::kKernelSweep || sweep2;
     // The sweep is timed per call, one pair of events around its n back-to-back launches: an
     // event between every two launches costs about 5 % of the step.  The two-pass step is
     // timed per step, to split the density/psi pass from the fused pass.
@@ -550,9 +556,21 @@ int lbm_step(lbm_t *h, int n) {
         HIP_TRY(h, hipEventRecord(call_ev[0], h->stream));
         HIP_TRY(h, hipEventRecord(call_ev[1], h->stream));
     }
-    for (int it = 0; it < n; ++it) {
+    int it = 0;
+    if (sweep2) {  // pairs of steps in one launch each; an odd last step by the one-step sweep
+        for (; it + 2 <= n; it += 2) {
+            HIP_TRY(h, pplbm::launch_sweep2(h->p, h->prec, h->launch, h->f[h->cur],
+                                            h->f[1 - h->cur], h->stream));
+            h->cur = 1 - h->cur;
+            h->step += 2;
+        }
+    }
+    for (; it < n; ++it) {
         float *fc = h->f[h->cur], *fn = h->f[1 - h->cur];
-        if (sweep) {
+        if (sweep2) {
+            pplbm::Launch one = default_launch(h->p.nx, h->p.ny);
+            HIP_TRY(h, pplbm::launch_sweep(h->p, h->prec, one, fc, fn, h->stream));
+        } else if (sweep) {
             HIP_TRY(h, pplbm::launch_sweep(h->p, h->prec, h->launch, fc, fn, h->stream));
         } else {
             hipEvent_t *ev = nullptr;

@@ -39,7 +39,7 @@ enum { kPrecF32 = 0, kPrecF64 = 1, kPrecMixed = 2 };
 constexpr int kFlagNT = 1;   // non-temporal stores of the new populations
 constexpr int kFlagXCD = 2;  // XCD-aware order of the tiles
 constexpr int kFlagShallow = 4;  // sweep: prefetch one row ahead instead of two
-enum { kKernelTwoPass = 0, kKernelSweep = 1 };
+enum { kKernelTwoPass = 0, kKernelSweep = 1, kKernelSweep2 = 2 };
 
 // Shape of the step launch.  Two-pass: (tx, ty) is the fused pass's tile.  Sweep: tx columns
 // per workgroup, ty rows per segment.
@@ -65,6 +65,10 @@ hipError_t launch_fused(const Physics &p, int prec, const Launch &L, const float
 // Whole step in one pass (psi recomputed from f along a sweep): fin -> fout.
 hipError_t launch_sweep(const Physics &p, int prec, const Launch &L, const float *fin,
                         float *fout, hipStream_t stream);
+// Two time steps per launch (temporal blocking); L.tx threads per workgroup (64-lane
+// independent strips), L.ty rows per segment.  Populations below 4 GiB.
+hipError_t launch_sweep2(const Physics &p, int prec, const Launch &L, const float *fin,
+                         float *fout, hipStream_t s);
 
 // f = f^eq(rho0, u0) (Eq. 2); rho0 [ny*nx], u0 [ny*nx*2] or null, device FP64.
 // Radial-profile initial state: log_rho holds 64 values (host memory, passed by value).

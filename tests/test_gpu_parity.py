@@ -338,3 +338,31 @@ def test_sweep_beyond_4gib_rows(L):
         vref = max(vref, np.abs(fl["vx"][inner]).max(), np.abs(fl["vy"][inner]).max())
     say(f"    all windows: rho {e_rho:.3e}  v {dv / vref:.3e}")
     assert e_rho < TOL and dv / vref < TOL
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (4, 256), (61, 61), (200, 77), (300, 130), (520, 9)])
+def test_two_step_sweep_is_bitwise_the_one_step_sweep(L, shape):
+    """Two time steps per launch (wave strips of 60 output columns, step t+1 two rows behind
+    step t, x-neighbours by lane shifts) against the one-step sweep: the same populations bit
+    for bit after even and odd step counts, for ragged and tiny lattices, several workgroup
+    sizes and segment heights, three forcing/collision pairs and every precision."""
+    nx, ny = shape
+    for scheme, coll in (("GUO_LI", "MRT"), ("EDM", "BGK"), ("SC", "BGK")):
+        wl = workload("droplet_4096_mrt", nx=nx, ny=ny, R=max(1.0, min(nx, ny) / 4),
+                      T_over_Tc=0.6, scheme=scheme, collision=coll,
+                      A=-0.26 if scheme != "GUO_LI" else 0.0)
+        rho0 = initial_density(wl)
+        precs = ("mixed", "f32", "f64") if scheme == "GUO_LI" else ("mixed",)
+        for prec in precs:
+            ref = gpu_lattice(L, wl, PRECISIONS[prec])
+            ref.init(rho0)
+            for tx, ty, steps in ((64, 1, 6), (256, 5, 7), (128, 32, 10)):
+                say(f"[two-step sweep] {nx}x{ny} {scheme}/{coll} {prec} tx {tx} ty {ty} {steps}")
+                lat = gpu_lattice(L, wl, PRECISIONS[prec])
+                lat.set_launch(L.LBM_KERNEL_SWEEP2, tx, ty, 0)
+                lat.init(rho0)
+                lat.step(steps)
+                one = gpu_lattice(L, wl, PRECISIONS[prec])
+                one.init(rho0)
+                one.step(steps)
+                assert np.array_equal(lat.populations(), one.populations()), (tx, ty, steps)
