@@ -4,18 +4,20 @@ Workload (default): the 4096 x 4096 periodic static droplet, radius 600, tanh in
 width 5 from the Maxwell coexistence densities at T/Tc = 0.5 (ratio ~725), MRT collision
 (s_rho = s_j = 1, s_e = s_eps = s_q = 1.1, s_nu = 1/tau, tau = 1), Guo forcing with Li's
 modified force term (sigma = 0.125), Carnahan-Starling EOS rescaled by K = 1/49.
-A step is one full time step -- by default the one-pass sweep kernel (psi recomputed from the
-populations, force, forcing, collision and streaming in one launch); --kernel two_pass runs the
-density/psi pass and the fused pass instead -- and the FP64 observables reduction runs every
---stats-every steps inside the timed region, as a production run would.  Inputs are resident in
-HBM before timing starts.  The sweep runs the library's default launch
-(512-column strips, 8-row segments, two rows of loads in flight, XCD-ordered tiles: the
-fastest shape measured on this workload and on 2048^2 to 8192^2 lattices); --autotune lets the library's autotuner pick
-(timed trials on the initial state, which it restores, before the warm-up), --launch sets it.
+A step is one full time step (psi from the populations, force, forcing, collision, streaming)
+and the FP64 observables reduction runs every --stats-every steps inside the timed region, as a
+production run would.  Inputs are resident in HBM before timing starts.  By default the library's
+default launch runs: the two-step sweep (two time steps per pass over HBM, 64-lane strips of 58
+output columns over 24-row segments); --kernel sweep runs the one-step sweep (512-column strips,
+8-row segments, two rows of loads in flight, XCD-ordered tiles), --kernel two_pass the
+density/psi pass and the fused pass; --autotune lets the library's autotuner pick (timed
+trials on the initial state, which it restores, before the warm-up), --launch sets the shape.
 
-Prints ONE JSON line: MLUPS, the HBM roofline of the dominant kernel measured with HIP events
-on the lattice's stream (algorithmic bytes per launch / average launch time), the same for the
-two-pass variant, and the FP64 oracle's MLUPS on the host cores (cpu_baseline).
+Prints ONE JSON line: MLUPS, the roofline of the dominant kernel measured with HIP events on the
+lattice's stream (the two-step sweep against the vector ALU peak -- algorithmic flops per launch
+/ average launch time -- with its HBM figures and its VALU issue rate alongside; the one-step
+kernels against HBM), the same for the alternative kernel, and the FP64 oracle's MLUPS on the
+host cores (cpu_baseline).
 
 --copy-probe instead times the library's plain copy kernel on a buffer the size of one
 population buffer (the scale reference for the HBM counters).
@@ -34,6 +36,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public spec
 SWEEP_BYTES_PER_NODE = 72      # one-pass step: 9 FP32 populations read + 9 written
+# Floating-point operations of one node's update on this workload's path (C-S EOS, MRT with Guo
+# and Li, mixed precision), counted in the compiled update: 2 per FMA, 1 per add, multiply,
+# reciprocal or square root; conversions, moves and lane shifts count 0.
+FLOPS_PER_NODE_STEP = 248
+# Vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, for
+# FP64 and unpacked FP32 alike; and the VALU issue peak, 1024 SIMDs x 16 lanes x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+VALU_LANE_OPS_PEAK = 1024 * 16 * 2.4e9
 FUSED_BYTES_PER_NODE = 76      # two-pass, pass 2: 9 populations read + 9 written + psi read
 PSI_BYTES_PER_NODE = 40        # two-pass, pass 1: 9 populations read + psi written
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
@@ -46,7 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="droplet_4096_mrt")
     ap.add_argument("--precision", default="mixed", choices=["f32", "f64", "mixed"])
-    ap.add_argument("--kernel", default="sweep", choices=["sweep", "sweep2", "two_pass"])
+    ap.add_argument("--kernel", default="sweep2", choices=["sweep2", "sweep", "two_pass"],
+                    help="sweep2: two steps per launch (the library's default); sweep: one step")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the sweep's launch with the library's autotuner first")
     ap.add_argument("--launch", default=None,
@@ -116,11 +127,11 @@ def make_lattice(lbm, wl, args, kernel):
                       lbm.make_collision(wl["collision"], s=s[:5]), wl["tau"],
                       precision=PRECISIONS[args.precision],
                       layout=lbm.LBM_LAYOUT_ROWS if args.layout == "rows" else lbm.LBM_LAYOUT_PLANES)
-    k, tx, ty, fl = lat.get_launch()
+    k, tx, ty, fl = lat.get_launch()  # the library's default: the two-step sweep
     if kernel == "two_pass":
         k, tx, ty, fl = lbm.LBM_KERNEL_TWO_PASS, 128, 8, lbm.LBM_LAUNCH_XCD_ORDER
-    if kernel == "sweep2":
-        k, tx, ty, fl = lbm.LBM_KERNEL_SWEEP2, 256, 32, 0
+    if kernel == "sweep":  # the one-step sweep's default shape on this lattice
+        k, tx, ty, fl = lbm.LBM_KERNEL_SWEEP, 512, 8, lbm.LBM_LAUNCH_XCD_ORDER
     if args.launch and kernel == args.kernel:
         v = [int(t) for t in args.launch.split(",")]
         tx, ty = v[0], v[1]
@@ -200,7 +211,7 @@ def main():
     lat = make_lattice(lbm, wl, args, args.kernel)
     lat.init(rho0)
     tuned_ms = None
-    if args.kernel == "sweep" and not args.launch and args.autotune:
+    if args.kernel != "two_pass" and not args.launch and args.autotune:
         # the library's autotuner (timed trials on this state, restored afterwards), before
         # the warm-up and outside the timed region
         tuned_ms = lat.autotune(None, trial_steps=50)
@@ -228,6 +239,13 @@ def main():
                         "two_pass": "fused_kernel"}[kernel],
              "bytes_per_node": per_node, "steps_per_launch": steps_per_launch,
              "avg_us": round(avg * 1e6, 2)}
+        if kernel == "sweep2":
+            # Two steps per pass over HBM: the kernel is bound by vector ALU issue, not HBM.
+            tflops = FLOPS_PER_NODE_STEP * steps_per_launch * nodes / avg / 1e12
+            hbm = {k: r[k] for k in ("achieved", "peak", "unit", "frac", "bytes_per_node")}
+            r.update(bound="alu", achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS,
+                     unit="TFLOP/s", frac=round(tflops / ALU_PEAK_TFLOPS, 4),
+                     flops_per_node_step=FLOPS_PER_NODE_STEP, hbm=hbm)
         if kernel == "two_pass":
             pavg = psi_ms / 1e3 / nt
             r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),
@@ -241,6 +259,12 @@ def main():
                 r["traffic"] = t[key]["bytes_per_launch"]
                 r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] /
                                                       (per_node * nodes), 4)
+                if "valu_insts_per_launch" in t[key]:  # wave instructions (SQ_INSTS_VALU)
+                    lane_ops = 64 * t[key]["valu_insts_per_launch"] / avg
+                    r["valu_issue"] = {"achieved": round(lane_ops / 1e12, 2),
+                                       "peak": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                                       "unit": "T lane-instructions/s",
+                                       "frac": round(lane_ops / VALU_LANE_OPS_PEAK, 4)}
         return r
 
     mlups = nodes * args.steps / elapsed / 1e6
@@ -258,7 +282,7 @@ def main():
                    "stats_every": args.stats_every, "parallelism": "single GPU"},
         "roofline": roofline(args.kernel, ev, launch) if ev else None,
     }
-    alt = "two_pass" if args.kernel == "sweep" else "sweep"
+    alt = "sweep" if args.kernel == "sweep2" else ("two_pass" if args.kernel == "sweep" else "sweep")
     if timing and args.alt_steps:
         lat = make_lattice(lbm, wl, args, alt)
         alt_launch = lat.get_launch()

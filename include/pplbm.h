@@ -156,8 +156,11 @@ int lbm_set_layout(lbm_t *h, int layout);
 int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
- * the sweep with tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER,
- * narrowed (tx, then ty) on small lattices until the launch has about 1024 workgroups.
+ * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, ty = 24) when the lattice is below 4 GiB of
+ * populations and gives at least 2048 strips of 58 x 24 nodes (from about 2048^2); otherwise
+ * -- and for the odd last step of the two-step sweep -- the one-step sweep with tx = 512,
+ * ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then ty) on small
+ * lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
  *     reads it; (tx, ty) = threads per workgroup of the fused pass (tx a multiple of 64,
  *     tx * ty <= 1024).  116 bytes of memory traffic per node and step.
@@ -170,7 +173,7 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *     4 GiB takes the two-pass step (LBM_EINVAL for the sweep; lbm_set_layout switches it).
  *     The batch's lattices must stay below 4 GiB each.
  *   LBM_KERNEL_SWEEP2: two time steps per launch (temporal blocking): each 64-lane wave sweeps
- *     a strip of 60 output columns over segments of ty rows, computing step t on its 64
+ *     a strip of 58 output columns over segments of ty rows, computing step t on its 64
  *     columns and step t+1 two rows behind; lanes exchange x-neighbours by DPP shifts, so no
  *     LDS or barrier is used, and only step t+1 is written: 72 bytes per node per two steps
  *     plus the strip and segment overlaps.  tx = threads per workgroup (independent waves,
@@ -222,10 +225,11 @@ int lbm_load(lbm_t *h, const char *path);
  * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. Synchronises. */
 int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 
-/* Autotuner: times trial_steps steps of the one-pass sweep for strip widths tx in {64, 128,
- * 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets XCD|SHALLOW, SHALLOW,
- * XCD, XCD|SHALLOW|NONTEMPORAL (shapes are bitwise equivalent, so only speed differs), keeps the
- * fastest and applies it with lbm_set_launch.  Runs on the current state, which it saves and
+/* Autotuner: times trial_steps steps (rounded up to even) of the one-pass sweep for strip widths
+ * tx in {64, 128, 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets
+ * XCD|SHALLOW, SHALLOW, XCD, XCD|SHALLOW|NONTEMPORAL, and (below 4 GiB) of the two-step sweep
+ * for tx in {64, 128, 256} and ty in {16, 32, 48, 64} (shapes are bitwise equivalent, so only
+ * speed differs), keeps the fastest and applies it with lbm_set_launch.  Runs on the current state, which it saves and
  * restores (populations and step count), so the simulation resumes exactly where it was.
  * cache_path (may be NULL): JSON lines keyed by device, size, scheme, collision, precision and
  * layout; a hit applies the cached launch without trials (*ms_out = -1).  *ms_out (may be

@@ -359,7 +359,17 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     h->p = p;
     h->xa = nx / 2;
     h->ya = ny / 2;
-    h->launch = default_launch(nx, ny);  // beyond 4 GiB the sweep takes per-row resources
+    // Two steps per launch (256 x 24) below 4 GiB of populations when the lattice gives the
+    // GPU at least 2048 wave strips (about half its wave slots; 2048^2 and up measured faster,
+    // 1024^2 slower); otherwise the one-step sweep, with per-row resources beyond 4 GiB.
+    h->launch = default_launch(nx, ny);
+    const long long strips2 = (long long)((nx + 57) / 58) * ((ny + 23) / 24);
+    if (pplbm::pop_bytes(p) <= pplbm::kSweepMaxBytes && strips2 >= 2048) {
+        h->launch.kernel = pplbm::kKernelSweep2;
+        h->launch.tx = 256;
+        h->launch.ty = 24;
+        h->launch.flags = 0;
+    }
     *out = h;
     return LBM_OK;
 }
@@ -631,33 +641,45 @@ int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_o
     if (he == hipSuccess) he = hipEventCreate(&e1);
     pplbm::Launch best = before;
     double best_ms = 1e300;
+    // one timed trial of a shape (an even number of steps, so both kernels compare per step)
+    const int nsteps = trial_steps + (trial_steps & 1);
+    auto trial = [&](int kernel, int tx, int ty, int fl) {
+        rc = lbm_set_launch(h, kernel, tx, ty, fl);
+        if (!rc) rc = lbm_step(h, 2);  // warm-up (first-launch costs)
+        if (rc) return;
+        he = hipEventRecord(e0, h->stream);
+        if (he == hipSuccess) rc = lbm_step(h, nsteps);
+        if (he == hipSuccess && !rc) he = hipEventRecord(e1, h->stream);
+        if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
+        float ms = 0;
+        if (he == hipSuccess && !rc) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && !rc && ms / nsteps < best_ms) {
+            best_ms = ms / nsteps;
+            best = h->launch;
+        }
+    };
     const int txs[] = {64, 128, 256, 512};
     const int tys[] = {4, 8, 16, 32, 64};
     const int fls[] = {pplbm::kFlagXCD | pplbm::kFlagShallow, pplbm::kFlagShallow,
                        pplbm::kFlagXCD, pplbm::kFlagXCD | pplbm::kFlagShallow | pplbm::kFlagNT};
     const int width = (int)std::min<size_t>(h->p.pitch, 512);
     for (int tx : txs) {
-        if (he != hipSuccess || rc) break;
         if (tx > 64 && tx > width) continue;  // strips wider than the lattice only idle
         for (int ty : tys) {
             if (ty > 8 && ty / 2 >= h->p.ny) continue;
             for (int fl : fls) {
                 if (he != hipSuccess || rc) break;
-                rc = lbm_set_launch(h, LBM_KERNEL_SWEEP, tx, ty, fl);
-                if (!rc) rc = lbm_step(h, 2);  // warm-up (first-launch costs)
-                if (rc) break;
-                he = hipEventRecord(e0, h->stream);
-                if (he == hipSuccess) rc = lbm_step(h, trial_steps);
-                if (he == hipSuccess && !rc) he = hipEventRecord(e1, h->stream);
-                if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
-                float ms = 0;
-                if (he == hipSuccess && !rc) he = hipEventElapsedTime(&ms, e0, e1);
-                if (he == hipSuccess && !rc && ms / trial_steps < best_ms) {
-                    best_ms = ms / trial_steps;
-                    best = h->launch;
-                }
+                trial(LBM_KERNEL_SWEEP, tx, ty, fl);
             }
         }
+    }
+    if (pplbm::pop_bytes(h->p) <= pplbm::kSweepMaxBytes) {  // two steps per launch
+        for (int tx : {64, 128, 256})
+            for (int ty : {16, 32, 48, 64}) {
+                if (he != hipSuccess || rc) break;
+                if (ty > 16 && ty / 2 >= h->p.ny) continue;
+                trial(LBM_KERNEL_SWEEP2, tx, ty, 0);
+            }
     }
     // restore the state whatever happened
     hipError_t he2 = hipMemcpyAsync(h->f[cur0], saved, fbytes, hipMemcpyDeviceToDevice, h->stream);

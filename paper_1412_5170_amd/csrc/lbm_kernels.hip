@@ -687,13 +687,15 @@ sweep_kernel_w5(const float *__restrict__ fin, float *__restrict__ fout, StepCon
 }
 
 // ---------------------------------------------------------------------------------------
-// Two steps per pass (temporal blocking).  Each wave owns a strip of 64 columns: its inner 60
-// are its output, the two on either side are recomputed by the neighbouring strips.  It sweeps
-// a segment of rows computing step t on every lane and step t + 1 two rows behind on the inner
-// lanes.  x-neighbours -- psi of either step, and the populations of step t that stream along
-// x -- move between lanes by whole-wave DPP shifts; y-neighbours stay in registers; so a wave
-// needs no LDS and no barrier, and only step t + 1 goes back to memory: half the HBM traffic
-// per step.  Same per-node arithmetic as the one-step sweep, so the same bits.
+// Two steps per pass (temporal blocking).  Each wave owns a strip of 64 columns and sweeps a
+// segment of rows, computing step t on every lane and step t + 1 two rows behind.  x-neighbours
+// -- psi of either step, and the populations of step t that stream along x -- move between
+// lanes by whole-wave DPP shifts; y-neighbours stay in registers; so a wave needs no LDS and no
+// barrier, and only step t + 1 goes back to memory: half the HBM traffic per step.  Each step
+// loses one lane of validity on either side (step t is right on lanes 1..62, the streamed
+// populations of step t + 1 on 2..61, step t + 1 on 3..60), so a strip outputs its inner 58
+// columns and neighbouring strips overlap by 6.  Same per-node arithmetic as the one-step
+// sweep, so the same bits.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ float lane_below(float v) {  // lane i receives lane i - 1
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
@@ -702,60 +704,42 @@ __device__ __forceinline__ float lane_above(float v) {  // lane i receives lane 
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-constexpr int kSweep2Out = 60;  // output columns of a 64-lane strip
+constexpr int kSweep2Out = 58;  // output columns of a 64-lane strip (lanes 3..60)
 
 template <typename R, typename D, int SCHEME, int COLL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
               int nstrips, int ntiles) {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the wave's tile: uniform across the wave (a scalar), so that row offsets stay scalar
+    // operands of the buffer accesses
+    const int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= ntiles) return;  // whole waves
     const int nx = c.nx, ny = c.ny;
-    const int xw = (t % nstrips) * kSweep2Out;  // first output column of the strip
+    const int xw = (t % nstrips) * kSweep2Out;  // first output column of the strip (lane 3)
     const int y0 = (t / nstrips) * H, y1 = y0 + H < ny ? y0 + H : ny;
     auto wrapx = [&](int xx) { xx %= nx; return xx < 0 ? xx + nx : xx; };
     auto wrapy = [&](int yy) { yy %= ny; return yy < 0 ? yy + ny : yy; };
-    const int x = wrapx(xw - 2 + lane);
-    const bool out = lane >= 2 && lane < 62 && xw + lane - 2 < nx;
-    const bool halo = lane < 2;  // lane 0: the column left of lane 0, lane 1: right of lane 63
-    const int hcol = lane == 0 ? wrapx(xw - 3) : wrapx(xw + 62);
+    const int x = wrapx(xw - 3 + lane);
+    const bool out = lane >= 3 && lane < 3 + kSweep2Out && xw + lane - 3 < nx;
     const bool nt = c.flags & kFlagNT;
     const __amdgpu_buffer_rsrc_t rin = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
     const unsigned qs = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
-    const unsigned vx = 4u * x, vh = 4u * hcol;
-    // x-neighbours of a row of psi: own lanes shifted, the strip's edges from the halo lanes
-    auto west = [&](float p, float h) {
-        const float w = lane_below(p);
-        return lane == 0 ? h : w;
-    };
-    auto east = [&](float p, float h) {
-        const float e = lane_above(p);
-        const float hr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h), 1));
-        return lane == 63 ? hr : e;
-    };
+    const unsigned vx = 4u * x;
 
     // step t: populations of rows s (fa), s+1 (fb), s+2 (fc, loads in flight); psi of rows
-    // s-1, s, s+1 for the own column (pm, pc, pn) and the halo column (hm, hh, hn)
+    // s-1, s, s+1 (pm, pc, pn)
     const int s0 = y0 - 2;
-    float fa[9], fb[9], fc[9], hc[9];
-    float pm, pc, pn = 0.f, hm = 0.f, hh = 0.f, hn = 0.f;
+    float fa[9], fb[9], fc[9];
     D ra, rb;
     bload9(rin, vx, fr * wrapy(s0 - 1), qs, fc);
-    pm = c.psi_of(fc);
+    float pm = c.psi_of(fc);
     bload9(rin, vx, fr * wrapy(s0), qs, fa);
     ra = density9<D>(fa);
-    pc = c.psi_of_rho(ra);
+    float pc = c.psi_of_rho(ra);
     bload9(rin, vx, fr * wrapy(s0 + 1), qs, fb);
-    if (halo) {
-        bload9(rin, vh, fr * wrapy(s0 - 1), qs, hc);
-        hm = c.psi_of(hc);
-        bload9(rin, vh, fr * wrapy(s0), qs, hc);
-        hh = c.psi_of(hc);
-        bload9(rin, vh, fr * wrapy(s0 + 1), qs, hc);
-    }
     // step t+1: the populations of row s-1 streamed so far (planes 0,1,3 from row s-1, planes
-    // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete with its
+    // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete (g) with its
     // density, and psi of rows s-3 and s-2
     float a0 = 0.f, a1 = 0.f, a3 = 0.f, b2 = 0.f, b5 = 0.f, b6 = 0.f, c2 = 0.f, c5 = 0.f,
           c6 = 0.f;
@@ -767,16 +751,12 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
         const int s = s0 + k;
         if (k + 1 < nrow) bload9(rin, vx, fr * wrapy(s + 2), qs, fc);
         rb = density9<D>(fb);
-        pn = c.psi_of_rho(rb);
-        if (halo) {
-            hn = c.psi_of(hc);
-            if (k + 1 < nrow) bload9(rin, vh, fr * wrapy(s + 2), qs, hc);
-        }
-        // step t, row s
+        const float pn = c.psi_of_rho(rb);
+        // step t, row s (right on lanes 1..62)
         float fs[9];
         {
-            const Nb<float> nb = {pc, east(pc, hh), west(pc, hh), pn, pm,
-                                  east(pn, hn), west(pn, hn), west(pm, hm), east(pm, hm)};
+            const Nb<float> nb = {pc, lane_above(pc), lane_below(pc), pn, pm,
+                                  lane_above(pn), lane_below(pn), lane_below(pm), lane_above(pm)};
             collide<R, D, SCHEME, COLL>(fa, nb, c, fs, ra);
         }
         // stream along x between lanes; along y into the rows held in registers
@@ -794,7 +774,7 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
         a3 = w3;
         const D r1 = density9<D>(f1);
         const float qn = c.psi_of_rho(r1);
-        // step t+1, row s-2
+        // step t+1, row s-2 (right on lanes 3..60)
         if (k >= 4) {
             const Nb<float> nb = {qc, lane_above(qc), lane_below(qc), qn, qm,
                                   lane_above(qn), lane_below(qn), lane_below(qm), lane_above(qm)};
@@ -809,8 +789,6 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
         qc = qn;
         pm = pc;
         pc = pn;
-        hm = hh;
-        hh = hn;
         ra = rb;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {

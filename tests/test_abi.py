@@ -170,7 +170,9 @@ def test_launch_rules_beyond_4gib():
     """Host-side launch rules (no GPU call is made): a lattice above 4 GiB per population
     buffer keeps the one-pass sweep in the rows layout (per-row buffer resources); switching it
     to the planes layout moves it to the two-pass step, and the sweep is then refused.  The
-    default shape is 512 x 8 with two rows in flight and XCD order; small lattices narrow it."""
+    default below 4 GiB on a large lattice is the two-step sweep (256 x 24); beyond 4 GiB, and
+    on small lattices, the one-step sweep (512 x 8 with two rows in flight and XCD order,
+    narrowed on small lattices)."""
     from paper_1412_5170_amd import lbm
     eos, frc, coll = lbm.make_eos(0.5, K=1 / 49), lbm.make_force("GUO_LI", sigma=0.125), \
         lbm.make_collision("MRT")
@@ -199,11 +201,20 @@ def test_launch_rules_beyond_4gib():
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 512, 8, 0) == lbm.LBM_OK
     lbm.lbm_destroy(big)
     small = create(4096, 4096)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
     assert lbm.lbm_set_layout(small, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
-    assert launch(small) == (lbm.LBM_KERNEL_SWEEP, 512, 8, lbm.LBM_LAUNCH_XCD_ORDER)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
     lbm.lbm_destroy(small)
+    mid = create(1024, 1024)  # too few strips for the two-step sweep to fill the GPU
+    assert launch(mid)[0] == lbm.LBM_KERNEL_SWEEP
+    lbm.lbm_destroy(mid)
+    big = create(10944, 10944)
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 32, 0) == lbm.LBM_EINVAL
+    lbm.lbm_destroy(big)
     tiny = create(300, 130)
     k, tx, ty, _ = launch(tiny)
     assert k == lbm.LBM_KERNEL_SWEEP and tx <= 512 and ty <= 8
     assert ((300 + tx - 1) // tx) * ((130 + ty - 1) // ty) >= 64
+    assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 320, 32, 0) == lbm.LBM_EINVAL
+    assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(tiny)

@@ -342,7 +342,7 @@ def test_sweep_beyond_4gib_rows(L):
 
 @pytest.mark.parametrize("shape", [(3, 3), (4, 256), (61, 61), (200, 77), (300, 130), (520, 9)])
 def test_two_step_sweep_is_bitwise_the_one_step_sweep(L, shape):
-    """Two time steps per launch (wave strips of 60 output columns, step t+1 two rows behind
+    """Two time steps per launch (wave strips of 58 output columns, step t+1 two rows behind
     step t, x-neighbours by lane shifts) against the one-step sweep: the same populations bit
     for bit after even and odd step counts, for ragged and tiny lattices, several workgroup
     sizes and segment heights, three forcing/collision pairs and every precision."""
