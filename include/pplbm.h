@@ -156,9 +156,9 @@ int lbm_set_layout(lbm_t *h, int layout);
 int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
- * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, ty = 24) when the lattice is below 4 GiB of
- * populations and gives at least 2048 strips of 58 x 24 nodes (from about 2048^2); otherwise
- * -- and for the odd last step of the two-step sweep -- the one-step sweep with tx = 512,
+ * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, ty = 24) when the lattice gives at least
+ * 2048 strips of 58 x 24 nodes (from about 2048^2); otherwise -- and for the odd last step of
+ * the two-step sweep -- the one-step sweep with tx = 512,
  * ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then ty) on small
  * lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
@@ -177,8 +177,8 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *     columns and step t+1 two rows behind; lanes exchange x-neighbours by DPP shifts, so no
  *     LDS or barrier is used, and only step t+1 is written: 72 bytes per node per two steps
  *     plus the strip and segment overlaps.  tx = threads per workgroup (independent waves,
- *     multiple of 64, <= 256).  An odd last step of lbm_step runs the one-step sweep.  Below
- *     4 GiB of populations only.
+ *     multiple of 64, <= 256).  An odd last step of lbm_step runs the one-step sweep.  Beyond
+ *     4 GiB of populations it addresses rows like the one-step sweep (rows layout only).
  * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
  *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
  *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */

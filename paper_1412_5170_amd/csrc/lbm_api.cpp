@@ -359,12 +359,12 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     h->p = p;
     h->xa = nx / 2;
     h->ya = ny / 2;
-    // Two steps per launch (256 x 24) below 4 GiB of populations when the lattice gives the
-    // GPU at least 2048 wave strips (about half its wave slots; 2048^2 and up measured faster,
-    // 1024^2 slower); otherwise the one-step sweep, with per-row resources beyond 4 GiB.
+    // Two steps per launch (256 x 24) when the lattice gives the GPU at least 2048 wave strips
+    // (about half its wave slots; 2048^2 and up measured faster, 1024^2 slower), with per-row
+    // resources beyond 4 GiB of populations; otherwise the one-step sweep.
     h->launch = default_launch(nx, ny);
     const long long strips2 = (long long)((nx + 57) / 58) * ((ny + 23) / 24);
-    if (pplbm::pop_bytes(p) <= pplbm::kSweepMaxBytes && strips2 >= 2048) {
+    if (strips2 >= 2048) {
         h->launch.kernel = pplbm::kKernelSweep2;
         h->launch.tx = 256;
         h->launch.ty = 24;
@@ -433,7 +433,7 @@ int lbm_set_layout(lbm_t *h, int layout) {
     h->layout = layout;
     h->p.frow = layout == LBM_LAYOUT_ROWS ? 9 * h->p.pitch : h->p.pitch;
     h->p.fq = layout == LBM_LAYOUT_ROWS ? h->p.pitch : h->p.plane;
-    if (!sweep_fits(h) && h->launch.kernel == pplbm::kKernelSweep) {
+    if (!sweep_fits(h) && h->launch.kernel != pplbm::kKernelTwoPass) {
         h->launch.kernel = pplbm::kKernelTwoPass;  // planes beyond 4 GiB: 64-bit plane offsets
         h->launch.tx = 256;
         h->launch.ty = 4;
@@ -463,8 +463,9 @@ int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags) {
     } else if (kernel == LBM_KERNEL_SWEEP2) {
         if (tx < 64 || tx % 64 || tx > 256 || ty < 1)
             return fail(h, LBM_EINVAL, "two-step sweep: tx a multiple of 64 up to 256, ty >= 1 rows");
-        if (pplbm::pop_bytes(h->p) > pplbm::kSweepMaxBytes)
-            return fail(h, LBM_EINVAL, "two-step sweep: population buffer beyond 4 GiB");
+        if (!sweep_fits(h))
+            return fail(h, LBM_EINVAL,
+                        "two-step sweep: planes layout beyond 4 GiB (use the rows layout or the two-pass step)");
     } else if (kernel == LBM_KERNEL_SWEEP) {
         if (tx < 64 || tx % 64 || tx > 512 || ty < 1)
             return fail(h, LBM_EINVAL, "sweep: tx a multiple of 64 up to 512, ty >= 1 rows");

@@ -706,7 +706,7 @@ __device__ __forceinline__ float lane_above(float v) {  // lane i receives lane 
 
 constexpr int kSweep2Out = 58;  // output columns of a 64-lane strip (lanes 3..60)
 
-template <typename R, typename D, int SCHEME, int COLL>
+template <typename R, typename D, int SCHEME, int COLL, bool BIG = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
               int nstrips, int ntiles) {
@@ -723,21 +723,29 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
     const int x = wrapx(xw - 3 + lane);
     const bool out = lane >= 3 && lane < 3 + kSweep2Out && xw + lane - 3 < nx;
     const bool nt = c.flags & kFlagNT;
-    const __amdgpu_buffer_rsrc_t rin = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
+    const __amdgpu_buffer_rsrc_t rbuf = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
     const unsigned qs = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
     const unsigned vx = 4u * x;
+    // loads of row r (wrapped): the whole-buffer resource, or beyond 4 GiB the row's own
+    auto load_row = [&](int r, float v[9]) {
+        const int rr = wrapy(r);
+        if constexpr (BIG)
+            bload9(row_rsrc(fin, c.frow, c.ffloats, rr), vx, 0u, qs, v);
+        else
+            bload9(rbuf, vx, fr * rr, qs, v);
+    };
 
     // step t: populations of rows s (fa), s+1 (fb), s+2 (fc, loads in flight); psi of rows
     // s-1, s, s+1 (pm, pc, pn)
     const int s0 = y0 - 2;
     float fa[9], fb[9], fc[9];
     D ra, rb;
-    bload9(rin, vx, fr * wrapy(s0 - 1), qs, fc);
+    load_row(s0 - 1, fc);
     float pm = c.psi_of(fc);
-    bload9(rin, vx, fr * wrapy(s0), qs, fa);
+    load_row(s0, fa);
     ra = density9<D>(fa);
     float pc = c.psi_of_rho(ra);
-    bload9(rin, vx, fr * wrapy(s0 + 1), qs, fb);
+    load_row(s0 + 1, fb);
     // step t+1: the populations of row s-1 streamed so far (planes 0,1,3 from row s-1, planes
     // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete (g) with its
     // density, and psi of rows s-3 and s-2
@@ -749,7 +757,7 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
     const int nrow = y1 - y0 + 4;
     for (int k = 0; k < nrow; ++k) {
         const int s = s0 + k;
-        if (k + 1 < nrow) bload9(rin, vx, fr * wrapy(s + 2), qs, fc);
+        if (k + 1 < nrow) load_row(s + 2, fc);
         rb = density9<D>(fb);
         const float pn = c.psi_of_rho(rb);
         // step t, row s (right on lanes 1..62)
@@ -780,7 +788,12 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
                                   lane_above(qn), lane_below(qn), lane_below(qm), lane_above(qm)};
             float fo[9];
             collide<R, D, SCHEME, COLL>(g, nb, c, fo, r2);
-            if (out) bstream_out<R, D>(rout, c, x, wrapy(s - 2), fo, nt);
+            if (out) {
+                if constexpr (BIG)
+                    bstream_out_rows<R, D>(fout, c, x, wrapy(s - 2), fo, nt);
+                else
+                    bstream_out<R, D>(rout, c, x, wrapy(s - 2), fo, nt);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) g[q] = f1[q];
@@ -1247,6 +1260,7 @@ dim3 row_grid(int nx, int ny, int block) {
 #define PPLBM_PF1 , 1
 #define PPLBM_PF2 , 2
 #define PPLBM_PF1_BIG , 1, true
+#define PPLBM_BIG , true
 #define PPLBM_PF2_BIG , 2, true
 #define PPLBM_DISPATCH(KERNEL, R, D, p, grid, block, lds, s, ...) \
     PPLBM_DISPATCH_X(KERNEL, R, D, PPLBM_NOEXTRA, p, grid, block, lds, s, __VA_ARGS__)
@@ -1334,7 +1348,14 @@ hipError_t sweep2_dispatch(const Physics &p, const Launch &L, const float *fin, 
     const int nseg = (p.ny + L.ty - 1) / L.ty;
     const int ntiles = nstrips * nseg, wpg = L.tx / 64;
     const dim3 grid((unsigned)((ntiles + wpg - 1) / wpg));
-    PPLBM_DISPATCH(sweep2_kernel, R, D, p, grid, dim3(L.tx), 0, s, fin, fout, c, L.ty, nstrips, ntiles);
+    if (pop_bytes(p) > kSweepMaxBytes) {  // per-row resources (row-interleaved layout only)
+        if (p.fq != p.pitch) return hipErrorInvalidValue;
+        PPLBM_DISPATCH_X(sweep2_kernel, R, D, PPLBM_BIG, p, grid, dim3(L.tx), 0, s, fin, fout, c,
+                         L.ty, nstrips, ntiles);
+    } else {
+        PPLBM_DISPATCH(sweep2_kernel, R, D, p, grid, dim3(L.tx), 0, s, fin, fout, c, L.ty,
+                       nstrips, ntiles);
+    }
     return hipGetLastError();
 }
 }  // namespace

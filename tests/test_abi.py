@@ -168,8 +168,8 @@ def test_load_rejects_missing_and_foreign_files(tmp_path):
 
 def test_launch_rules_beyond_4gib():
     """Host-side launch rules (no GPU call is made): a lattice above 4 GiB per population
-    buffer keeps the one-pass sweep in the rows layout (per-row buffer resources); switching it
-    to the planes layout moves it to the two-pass step, and the sweep is then refused.  The
+    buffer keeps the sweeps in the rows layout (per-row buffer resources); switching it to the
+    planes layout moves it to the two-pass step, and both sweeps are then refused.  The
     default below 4 GiB on a large lattice is the two-step sweep (256 x 24); beyond 4 GiB, and
     on small lattices, the one-step sweep (512 x 8 with two rows in flight and XCD order,
     narrowed on small lattices)."""
@@ -192,13 +192,15 @@ def test_launch_rules_beyond_4gib():
     fb = ctypes.c_size_t()
     assert lbm.lbm_layout(big, None, None, ctypes.byref(fb), None) == lbm.LBM_OK
     assert fb.value > 2 ** 32
-    assert launch(big) == (lbm.LBM_KERNEL_SWEEP, 512, 8, lbm.LBM_LAUNCH_XCD_ORDER)
+    assert launch(big) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 256, 16, 0) == lbm.LBM_OK
     assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
     assert launch(big)[0] == lbm.LBM_KERNEL_TWO_PASS
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 512, 8, 0) == lbm.LBM_EINVAL
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_ROWS) == lbm.LBM_OK
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 512, 8, 0) == lbm.LBM_OK
+    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(big)
     small = create(4096, 4096)
     assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
@@ -208,9 +210,6 @@ def test_launch_rules_beyond_4gib():
     mid = create(1024, 1024)  # too few strips for the two-step sweep to fill the GPU
     assert launch(mid)[0] == lbm.LBM_KERNEL_SWEEP
     lbm.lbm_destroy(mid)
-    big = create(10944, 10944)
-    assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 32, 0) == lbm.LBM_EINVAL
-    lbm.lbm_destroy(big)
     tiny = create(300, 130)
     k, tx, ty, _ = launch(tiny)
     assert k == lbm.LBM_KERNEL_SWEEP and tx <= 512 and ty <= 8

@@ -286,10 +286,11 @@ def test_full_size_4096_sampled_windows(L):
 
 def test_sweep_beyond_4gib_rows(L):
     """A lattice whose population buffer exceeds 4 GiB (10944 x 10944: 4.31 GB per buffer)
-    runs the sweep with one buffer resource per row.  Its state after 20 steps must equal,
-    bit for bit, the two-pass step's (64-bit pointers), and match the oracle on windows that
-    lie beyond the first 4 GiB (rows above 10901), across the periodic wrap and at the
-    interface of a droplet centred near the last row."""
+    runs both sweeps with one buffer resource per row.  The two-step sweep (its default) and
+    the one-step sweep must equal, bit for bit after 20 steps, the two-pass step's state
+    (64-bit pointers), and match the oracle on windows that lie beyond the first 4 GiB (rows
+    above 10901), across the periodic wrap and at the interface of a droplet centred near the
+    last row."""
     import torch
     n, K, win = 10944, 20, 16
     wl = workload("droplet_4096_mrt", nx=n, ny=n)
@@ -298,22 +299,24 @@ def test_sweep_beyond_4gib_rows(L):
     cx, cy, R = n // 2 + 1234, n - 30, 150
     rho0 = np.roll(np.roll(inputs.droplet(n, n, float(R), 5.0, l, g), cy - n // 2, axis=0),
                    cx - n // 2, axis=1)
-    say(f"[parity > 4 GiB] {n}x{n} sweep vs two-pass, {K} steps")
+    say(f"[parity > 4 GiB] {n}x{n} two-step and one-step sweep vs two-pass, {K} steps")
     lats = []
-    for kernel in ("sweep", "two_pass"):
+    for kernel in ("sweep2", "sweep", "two_pass"):
         lat = gpu_lattice(L, wl, PRECISIONS["mixed"])
+        if kernel == "sweep":
+            lat.set_launch(L.LBM_KERNEL_SWEEP, 512, 8, L.LBM_LAUNCH_XCD_ORDER)
         if kernel == "two_pass":
             lat.set_launch(L.LBM_KERNEL_TWO_PASS, 256, 4, L.LBM_LAUNCH_XCD_ORDER)
-        assert lat.get_launch()[0] == (L.LBM_KERNEL_SWEEP if kernel == "sweep"
-                                       else L.LBM_KERNEL_TWO_PASS)
+        assert lat.get_launch()[0] == {"sweep2": L.LBM_KERNEL_SWEEP2, "sweep": L.LBM_KERNEL_SWEEP,
+                                       "two_pass": L.LBM_KERNEL_TWO_PASS}[kernel]
         lat.init(rho0)
         lat.step(K)
         lats.append(lat)
     torch.cuda.synchronize()
     assert lats[0].f_a.numel() * 4 > 2 ** 32
-    assert torch.equal(lats[0].f_a, lats[1].f_a)
-    say("    sweep == two-pass bitwise")
-    lats[1] = None
+    assert torch.equal(lats[0].f_a, lats[2].f_a) and torch.equal(lats[1].f_a, lats[2].f_a)
+    say("    two-step sweep == one-step sweep == two-pass bitwise")
+    lats[1] = lats[2] = None
     rho_g, u_g = lats[0].read()
     starts = [(cx + R - win // 2, cy - win // 2), (cx - R - win // 2, cy - win // 2),
               (cx - win // 2, (cy + R) % n - win // 2), (cx - win // 2, cy - R - win // 2),
