@@ -187,6 +187,7 @@ enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1, LBM_KERNEL_SWEEP2 = 2 };
 #define LBM_LAUNCH_XCD_ORDER 2
 #define LBM_LAUNCH_SHALLOW 4
 #define LBM_LAUNCH_SERIAL_KINDS 8 /* batch only: see lbm_batch_set_launch */
+#define LBM_LAUNCH_TWO_STEP 16    /* batch only: see lbm_batch_set_launch */
 int lbm_set_launch(lbm_t *h, int kernel, int tx, int ty, int flags);
 int lbm_get_launch(const lbm_t *h, int *kernel, int *tx, int *ty, int *flags);
 
@@ -266,11 +267,15 @@ void lbm_batch_destroy(lbm_batch_t *b);
 /* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups per kind
  * (0: one per tile up to 2048; rounded down to a multiple of 8, each XCD walking its own eighth
  * of the tile list), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW |
- * LBM_LAUNCH_SERIAL_KINDS.  The kinds (forcing scheme and collision) touch disjoint lattices,
- * so by default the captured graph holds one independent chain of launches per kind, which the
+ * LBM_LAUNCH_SERIAL_KINDS | LBM_LAUNCH_TWO_STEP.  The kinds (forcing scheme and collision)
+ * touch disjoint lattices, so by default the captured graph holds one independent chain of
+ * launches per kind, which the
  * GPU may run side by side; LBM_LAUNCH_SERIAL_KINDS captures them one after another on the
- * batch's stream instead.  Results are bitwise the same either way.  Default: tx = 256,
- * groups = 0, flags = 0 (the fastest measured on the 64-lattice droplet sweep). */
+ * batch's stream instead.  LBM_LAUNCH_TWO_STEP advances two steps per launch with the
+ * single lattice's two-step sweep (64-lane strips of 58 output columns, 24-row segments; with
+ * n = 2 mod 4 steps the last two are one-step launches).  Results are bitwise the same in every
+ * case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP (the 64-lattice droplet
+ * sweep to equilibrium: 56.8 s against 78.5 s with one step per launch). */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 
 /* Segment height (rows per tile) of lattice i; 0 (the default) is automatic: every time the

@@ -37,6 +37,9 @@ struct lbm_batch {
     void *desc = nullptr;            // device BatchLattice[count]
     int4 *tiles = nullptr;           // device tile list (capacity max_tiles)
     int2 *meta = nullptr;            // device (offset, count) of each kind's tiles
+    int4 *tiles2 = nullptr;          // two-step tile list: (lattice, first output column,
+    int2 *meta2 = nullptr;           //   first row, rows), and each kind's slice of it
+    size_t max_tiles2 = 0;
     std::vector<int> kinds;          // kinds present (scheme * 2 + collision), ascending
     size_t max_tiles = 0;
     // observables
@@ -46,7 +49,9 @@ struct lbm_batch {
     double *partial = nullptr, *out = nullptr;
     size_t max_sblocks = 0;
     // launch
-    int tx = 256, groups = 0, flags = 0;  // 256-column strips, two rows of loads in flight
+    // two steps per launch; one-step launches (the rest of a 2 mod 4 step count) with
+    // 256-column strips and two rows of loads in flight
+    int tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP;
     hipStream_t stream = nullptr;
     std::vector<hipStream_t> side;   // one more stream per kind beyond the first (capture only)
     hipEvent_t fork = nullptr;
@@ -92,6 +97,16 @@ size_t tiles_at(const lbm_batch *b, int i, int rows) {
 size_t tiles_max(const lbm_batch *b, int i) {
     return tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : kAutoRowsMin);
 }
+
+constexpr int kTwoStepRows = 24;  // segment height of the two-step tiles
+
+size_t tiles2_at(const lbm_batch *b, int i) {
+    const Physics &p = b->phys[i];
+    const int w = pplbm::sweep2_out_columns();
+    return (size_t)((p.nx + w - 1) / w) * ((p.ny + kTwoStepRows - 1) / kTwoStepRows);
+}
+
+bool two_step(const lbm_batch *b) { return b->flags & LBM_LAUNCH_TWO_STEP; }
 
 int upload_desc(lbm_batch *b) {
     const size_t sz = pplbm::batch_lattice_bytes();
@@ -149,6 +164,41 @@ int upload_tiles(lbm_batch *b) {
     if (!t.empty())
         BHIP(b, hipMemcpyAsync(b->tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->meta, meta.data(), meta.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    // the two-step tiles of the active lattices, grouped by kind in the same order
+    std::vector<int4> t2;
+    std::vector<int2> meta2;
+    if (two_step(b)) {
+        size_t need2 = 0;
+        for (int i = 0; i < b->count; ++i) need2 += tiles2_at(b, i);
+        if (need2 > b->max_tiles2) {
+            drop_graph(b);
+            if (b->tiles2) (void)hipFree(b->tiles2);
+            b->tiles2 = nullptr;
+            b->max_tiles2 = 0;
+            if (hipMalloc(&b->tiles2, need2 * sizeof(int4)) != hipSuccess) {
+                (void)hipGetLastError();
+                return bfail(b, LBM_ENOMEM, "two-step tile list allocation failed");
+            }
+            b->max_tiles2 = need2;
+        }
+        const int w = pplbm::sweep2_out_columns();
+        for (int kind : b->kinds) {
+            const int first = (int)t2.size();
+            for (int i = 0; i < b->count; ++i) {
+                if (!b->active[i]) continue;
+                const Physics &p = b->phys[i];
+                if (p.scheme * 2 + p.coll != kind) continue;
+                for (int y0 = 0; y0 < p.ny; y0 += kTwoStepRows)
+                    for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(make_int4(i, x0, y0, kTwoStepRows));
+            }
+            meta2.push_back(make_int2(first, (int)t2.size() - first));
+        }
+        if (!t2.empty())
+            BHIP(b, hipMemcpyAsync(b->tiles2, t2.data(), t2.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                   b->stream));
+        BHIP(b, hipMemcpyAsync(b->meta2, meta2.data(), meta2.size() * sizeof(int2), hipMemcpyHostToDevice,
+                               b->stream));
+    }
     BHIP(b, hipStreamSynchronize(b->stream));
     b->tiles_dirty = false;
     return LBM_OK;
@@ -163,12 +213,37 @@ int grid_groups(const lbm_batch *b) {
     return (int)g;
 }
 
+// Workgroups (of four waves) of a two-step launch: one wave per tile up to 4096 waves.
+int grid2_groups(const lbm_batch *b) {
+    size_t all = 0;
+    for (int i = 0; i < b->count; ++i) all += tiles2_at(b, i);
+    return (int)std::max<size_t>(std::min<size_t>((all + 3) / 4, 1024), 1);
+}
+
+// n (even) steps as launches: with two steps per launch, 2 (n / 4) two-step launches and the
+// rest (0 or 2) one-step launches, an even number of buffer swaps in all, so every lattice's
+// populations are back in f[0] after the n steps, as with n one-step launches.
+void step_plan(const lbm_batch *b, int n, int *two, int *one) {
+    *two = two_step(b) ? 2 * (n / 4) : 0;
+    *one = n - 2 * *two;
+}
+
+hipError_t launch_kind(lbm_batch *b, size_t j, bool two, int parity, hipStream_t s) {
+    if (two)
+        return pplbm::launch_batch2_kind(b->desc, b->tiles2, b->meta2, (int)j, b->kinds[j] / 2,
+                                         b->kinds[j] % 2, parity, grid2_groups(b), s);
+    return pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
+                                    b->kinds[j] % 2, parity, b->tx, grid_groups(b),
+                                    b->flags & pplbm::kFlagShallow, s);
+}
+
 int launch_steps(lbm_batch *b, int n) {
-    for (int k = 0; k < n; ++k)
+    int two, one;
+    step_plan(b, n, &two, &one);
+    int parity = 0;
+    for (int k = 0; k < two + one; ++k, parity ^= 1)
         for (size_t j = 0; j < b->kinds.size(); ++j)
-            BHIP(b, pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
-                                             b->kinds[j] % 2, k & 1, b->tx, grid_groups(b),
-                                             b->flags & pplbm::kFlagShallow, b->stream));
+            BHIP(b, launch_kind(b, j, k < two, parity, b->stream));
     return LBM_OK;
 }
 
@@ -182,12 +257,11 @@ int launch_steps_by_kind(lbm_batch *b, int n) {
         const hipError_t w = hipStreamWaitEvent(b->side[j - 1], b->fork, 0);
         if (e == hipSuccess) e = w;
     }
+    int two, one;
+    step_plan(b, n, &two, &one);
     for (size_t j = 0; j < nk; ++j) {
         hipStream_t s = j == 0 ? b->stream : b->side[j - 1];
-        for (int k = 0; k < n && e == hipSuccess; ++k)
-            e = pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
-                                         b->kinds[j] % 2, k & 1, b->tx, grid_groups(b),
-                                         b->flags & pplbm::kFlagShallow, s);
+        for (int k = 0; k < two + one && e == hipSuccess; ++k) e = launch_kind(b, j, k < two, k & 1, s);
     }
     for (size_t j = 1; j < nk; ++j) {
         hipError_t w = hipEventRecord(b->join[j - 1], b->side[j - 1]);
@@ -300,6 +374,7 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
     }
     ok = ok && hipMalloc(&b->desc, pplbm::batch_lattice_bytes() * count) == hipSuccess &&
          hipMalloc(&b->meta, 8 * sizeof(int2)) == hipSuccess &&
+         hipMalloc(&b->meta2, 8 * sizeof(int2)) == hipSuccess &&
          hipMalloc(&b->out, pplbm::kStatsOut * sizeof(double) * count) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -323,7 +398,8 @@ void lbm_batch_destroy(lbm_batch_t *b) {
         if (b->f1[i]) (void)hipFree(b->f1[i]);
         if (b->vprev[i]) (void)hipFree(b->vprev[i]);
     }
-    for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->meta, (void *)b->sblocks,
+    for (void *p : {(void *)b->desc, (void *)b->tiles, (void *)b->meta, (void *)b->tiles2,
+                    (void *)b->meta2, (void *)b->sblocks,
                     (void *)b->ranges, (void *)b->ids, (void *)b->partial, (void *)b->out})
         if (p) (void)hipFree(p);
     for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
@@ -337,9 +413,10 @@ int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags) {
     if (!b) return LBM_EINVAL;
     if (tx < 64 || tx % 64 || tx > 512 || groups < 0)
         return bfail(b, LBM_EINVAL, "tx: multiple of 64 up to 512; groups >= 0 (0 = automatic)");
-    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW | LBM_LAUNCH_SERIAL_KINDS))
-        return bfail(b, LBM_EINVAL,
-                     "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW, LBM_LAUNCH_SERIAL_KINDS");
+    if (flags & ~(LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW | LBM_LAUNCH_SERIAL_KINDS |
+                  LBM_LAUNCH_TWO_STEP))
+        return bfail(b, LBM_EINVAL, "batch flags: LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_SHALLOW, "
+                                    "LBM_LAUNCH_SERIAL_KINDS, LBM_LAUNCH_TWO_STEP");
     drop_graph(b);
     b->tx = tx;
     b->groups = groups;
@@ -606,7 +683,7 @@ int lbm_batch_autotune(lbm_batch_t *b, const char *cache_path, int trial_steps, 
     double best_ms = 1e300, ms = 0;
     // stage 1: strip width and prefetch depth at the current segment heights
     for (int tx : {64, 128, 256, 512}) {
-        for (int fl : {pplbm::kFlagShallow, 0}) {
+        for (int fl : {pplbm::kFlagShallow, 0, (int)LBM_LAUNCH_TWO_STEP}) {
             if (rc) break;
             rc = trial(tx, fl, rows0, &ms);
             if (!rc && ms < best_ms) {

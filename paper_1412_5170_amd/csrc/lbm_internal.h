@@ -111,6 +111,13 @@ hipError_t launch_batch_kind(const void *lats, const int4 *tiles, const int2 *me
                              int scheme, int coll, int parity, int tx, int groups, bool shallow,
                              hipStream_t s);
 
+// Two steps of one kind of the batch (f[parity] -> f[parity ^ 1]): groups workgroups of four
+// independent waves walk the kind's slice of the two-step tile list (lattice, first output
+// column, first row, rows), each tile a strip of sweep2_out_columns() output columns.
+hipError_t launch_batch2_kind(const void *lats, const int4 *tiles, const int2 *meta, int kind,
+                              int scheme, int coll, int parity, int groups, hipStream_t s);
+int sweep2_out_columns();
+
 // Observables of the lattices listed in ids (nlat of them) from f[parity]: sblocks[b] =
 // (lattice, chunk, chunks, partial slot); ranges[i] = (first partial, count) of ids[i]; out
 // receives kStatsOut doubles per lattice id.

@@ -706,18 +706,15 @@ __device__ __forceinline__ float lane_above(float v) {  // lane i receives lane 
 
 constexpr int kSweep2Out = 58;  // output columns of a 64-lane strip (lanes 3..60)
 
-template <typename R, typename D, int SCHEME, int COLL, bool BIG = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
-sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
-              int nstrips, int ntiles) {
+// One wave's tile: the strip whose first output column is xw (on lane 3), rows [y0, y0 + H)
+// (clipped at ny); xw, y0 and H are wave-uniform.
+template <typename R, typename D, int SCHEME, int COLL, bool BIG>
+__device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
+                                            float *__restrict__ fout, const StepConst<R, D> &c,
+                                            int xw, int y0, int H) {
     const int lane = threadIdx.x & 63;
-    // the wave's tile: uniform across the wave (a scalar), so that row offsets stay scalar
-    // operands of the buffer accesses
-    const int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t >= ntiles) return;  // whole waves
     const int nx = c.nx, ny = c.ny;
-    const int xw = (t % nstrips) * kSweep2Out;  // first output column of the strip (lane 3)
-    const int y0 = (t / nstrips) * H, y1 = y0 + H < ny ? y0 + H : ny;
+    const int y1 = y0 + H < ny ? y0 + H : ny;
     auto wrapx = [&](int xx) { xx %= nx; return xx < 0 ? xx + nx : xx; };
     auto wrapy = [&](int yy) { yy %= ny; return yy < 0 ? yy + ny : yy; };
     const int x = wrapx(xw - 3 + lane);
@@ -811,6 +808,18 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
     }
 }
 
+template <typename R, typename D, int SCHEME, int COLL, bool BIG = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
+              int nstrips, int ntiles) {
+    // the wave's tile: uniform across the wave (a scalar), so that row offsets stay scalar
+    // operands of the buffer accesses
+    const int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= ntiles) return;  // whole waves
+    sweep2_tile<R, D, SCHEME, COLL, BIG>(fin, fout, c, (t % nstrips) * kSweep2Out,
+                                         (t / nstrips) * H, H);
+}
+
 // ---------------------------------------------------------------------------------------
 // Batched sweep: many independent lattices (own size, physics and relaxation) advanced by one
 // launch per kind of lattice and step.  Each workgroup walks its kind's slice of the shared
@@ -848,6 +857,25 @@ batch_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict_
         sweep_tile<float, double, SCHEME, COLL, PF>(L.f[parity], L.f[parity ^ 1], c, tl.y, tl.z,
                                                     tl.w, ring);
         __syncthreads();  // the ring is reused by the next tile
+    }
+}
+
+// Two steps per launch for one kind of the batch: every wave walks the kind's slice meta2[kind]
+// of the two-step tile list (lattice, first output column, first row, rows), one 64-lane strip
+// of 58 output columns per tile (the single lattice's two-step sweep, tile by tile).
+template <int SCHEME, int COLL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+batch2_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict__ tiles,
+                   const int2 *__restrict__ meta, int kind, int parity) {
+    const int2 m = meta[kind];
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int w = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int t = w; t < m.y; t += waves) {
+        const int4 tl = tiles[m.x + t];
+        const BatchLattice &L = lats[tl.x];
+        const StepConst<float, double> c = L.c;
+        sweep2_tile<float, double, SCHEME, COLL, false>(L.f[parity], L.f[parity ^ 1], c, tl.y,
+                                                        tl.z, tl.w);
     }
 }
 
@@ -1487,6 +1515,27 @@ hipError_t launch_batch_kind(const void *lats, const int4 *tiles, const int2 *me
 #undef PPLBM_KIND
     return hipGetLastError();
 }
+
+hipError_t launch_batch2_kind(const void *lats, const int4 *tiles, const int2 *meta, int kind,
+                              int scheme, int coll, int parity, int groups, hipStream_t s) {
+    const BatchLattice *L = reinterpret_cast<const BatchLattice *>(lats);
+    const dim3 g(groups), blk(256);
+#define PPLBM_KIND2(S, C) \
+    hipLaunchKernelGGL((batch2_kind_kernel<S, C>), g, blk, 0, s, L, tiles, meta, kind, parity)
+    switch (scheme * 2 + coll) {
+    case EDM * 2 + BGK: PPLBM_KIND2(EDM, BGK); break;
+    case GUO * 2 + BGK: PPLBM_KIND2(GUO, BGK); break;
+    case GUO_LI * 2 + BGK: PPLBM_KIND2(GUO_LI, BGK); break;
+    case SC * 2 + BGK: PPLBM_KIND2(SC, BGK); break;
+    case GUO * 2 + MRT: PPLBM_KIND2(GUO, MRT); break;
+    case GUO_LI * 2 + MRT: PPLBM_KIND2(GUO_LI, MRT); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef PPLBM_KIND2
+    return hipGetLastError();
+}
+
+int sweep2_out_columns() { return kSweep2Out; }
 
 hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblocks,
                               const int2 *ranges, const int *ids, int nlat, int parity, int track,

@@ -26,6 +26,7 @@ LBM_LAYOUT_PLANES, LBM_LAYOUT_ROWS = 0, 1
 LBM_KERNEL_TWO_PASS, LBM_KERNEL_SWEEP, LBM_KERNEL_SWEEP2 = 0, 1, 2
 LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_XCD_ORDER, LBM_LAUNCH_SHALLOW = 1, 2, 4
 LBM_LAUNCH_SERIAL_KINDS = 8
+LBM_LAUNCH_TWO_STEP = 16
 
 SCHEMES = {"EDM": LBM_FORCE_EDM, "GUO": LBM_FORCE_GUO, "GUO_LI": LBM_FORCE_GUO_LI,
            "SC": LBM_FORCE_SC}
@@ -343,7 +344,7 @@ class Batch:
     ny, T_over_Tc, K, scheme, A, sigma, collision, s (5 MRT rates), tau; "psi_eps" (with "G")
     selects the effective density of Eq. 33 instead of the Carnahan-Starling EOS."""
 
-    def __init__(self, members, tx=256, groups=0, flags=0):
+    def __init__(self, members, tx=256, groups=0, flags=LBM_LAUNCH_TWO_STEP):
         n = len(members)
         self.members = members
         nx = (ctypes.c_int * n)(*[m["nx"] for m in members])

@@ -46,11 +46,13 @@ def _single(L, m, steps, tx, rows):
     return lat.populations()
 
 
-@pytest.mark.parametrize("tx,flags", [(128, 4), (64, 0), (256, 4), (256, 12), (128, 8)])
+@pytest.mark.parametrize("tx,flags", [(128, 4), (64, 0), (256, 4), (256, 12), (128, 8), (256, 16),
+                                      (128, 24)])
 def test_batch_members_match_single_lattices_bitwise(L, tx, flags):
     """Five kinds (scheme, collision): by default one concurrent chain of launches per kind in
-    the captured graph, with LBM_LAUNCH_SERIAL_KINDS (8) one chain; the graph is replayed and
-    every replay is checked."""
+    the captured graph, with LBM_LAUNCH_SERIAL_KINDS (8) one chain; with LBM_LAUNCH_TWO_STEP
+    (16) two steps per launch (24 steps: six two-step launches per kind); the graph is replayed
+    and every replay is checked."""
     say(f"[batch bitwise] tx {tx} flags {flags}")
     b = L.Batch(MEMBERS, tx=tx, flags=flags)
     for i, m in enumerate(MEMBERS):
@@ -64,8 +66,9 @@ def test_batch_members_match_single_lattices_bitwise(L, tx, flags):
             assert np.array_equal(b.populations(i), ref), (replay, i)
 
 
-def test_batch_run_drops_converged_and_unstable(L):
-    say("[batch run]")
+@pytest.mark.parametrize("flags", [0, 16])
+def test_batch_run_drops_converged_and_unstable(L, flags):
+    say(f"[batch run] flags {flags}")
     members = [
         dict(nx=64, ny=64, T_over_Tc=0.8, K=1.0, scheme="GUO", A=-0.5, collision="BGK", tau=1.0),
         dict(nx=96, ny=96, T_over_Tc=0.7, K=0.3, scheme="GUO", A=-0.5, collision="MRT", tau=0.9),
@@ -73,7 +76,7 @@ def test_batch_run_drops_converged_and_unstable(L):
         # within 50 steps for this droplet
         dict(nx=64, ny=64, T_over_Tc=0.5, K=1.0, scheme="EDM", A=0.0, collision="BGK", tau=0.51),
     ]
-    b = L.Batch(members, tx=64)
+    b = L.Batch(members, tx=64, flags=flags)
     for i, m in enumerate(members):
         b.init(i, _rho0(m))
     steps, status = b.run(tol=1e-7, check_every=100, max_steps=40000, tol_rho=1e-7)
