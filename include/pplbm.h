@@ -156,11 +156,12 @@ int lbm_set_layout(lbm_t *h, int layout);
 int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
- * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, ty = 24) when the lattice gives at least
- * 2048 strips of 58 x 24 nodes (from about 2048^2); otherwise -- and for the odd last step of
- * the two-step sweep -- the one-step sweep with tx = 512,
- * ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then ty) on small
- * lattices until the launch has about 1024 workgroups.
+ * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, flags 0) on every lattice, with S =
+ * ceil(nx / 58) strips: ty = 16 where S * ceil(ny / 16) >= 8192 (from about 3000^2), else
+ * ty = 24 where S * ceil(ny / 24) >= 3072 (about 2048^2), else the ty between 6 and 24 that
+ * gives about 3200 waves.  The odd last step of an lbm_step call runs the one-step sweep with
+ * tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then
+ * ty) on small lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
  *     reads it; (tx, ty) = threads per workgroup of the fused pass (tx a multiple of 64,
  *     tx * ty <= 1024).  116 bytes of memory traffic per node and step.

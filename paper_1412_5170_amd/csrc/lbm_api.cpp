@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -359,16 +360,29 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     h->p = p;
     h->xa = nx / 2;
     h->ya = ny / 2;
-    // Two steps per launch (256 x 24) when the lattice gives the GPU at least 2048 wave strips
-    // (about half its wave slots; 2048^2 and up measured faster, 1024^2 slower), with per-row
-    // resources beyond 4 GiB of populations; otherwise the one-step sweep.
+    // Two steps per launch (256 threads, four waves of 58 output columns), with per-row
+    // resources beyond 4 GiB of populations.  Segment heights, measured on square MRT droplets:
+    // 16 rows where that makes at least 8192 waves (shorter waves balance better: +1 % at
+    // 4096^2, +3 % at 3000^2 and 6000^2, +4 % at 8192^2 over 24 rows); else 24 rows where that
+    // still makes about 3072 waves (2048^2: 16 rows would leave a short second round, 7 %
+    // slower); on smaller lattices the height that gives about 3200 waves, one resident round,
+    // but at least 6 rows, below which the recomputed rows of step t cost more than the extra
+    // waves gain (512^2: +14 %, 768^2: +21 %, 1024^2: +13 %, 1536^2: +7 % over the one-step
+    // sweep).  The one-step sweep's default shape serves the odd last step.
     h->launch = default_launch(nx, ny);
-    const long long strips2 = (long long)((nx + 57) / 58) * ((ny + 23) / 24);
-    if (strips2 >= 2048) {
+    {
+        const long long strips = (nx + 57) / 58;
         h->launch.kernel = pplbm::kKernelSweep2;
         h->launch.tx = 256;
-        h->launch.ty = 24;
         h->launch.flags = 0;
+        if (strips * ((ny + 15) / 16) >= 8192) {
+            h->launch.ty = 16;
+        } else if (strips * ((ny + 23) / 24) >= 3072) {
+            h->launch.ty = 24;
+        } else {
+            const long long segs = std::max(1LL, 3200 / strips);
+            h->launch.ty = (int)std::min(24LL, std::max(6LL, (ny + segs - 1) / segs));
+        }
     }
     *out = h;
     return LBM_OK;

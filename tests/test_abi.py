@@ -170,9 +170,9 @@ def test_launch_rules_beyond_4gib():
     """Host-side launch rules (no GPU call is made): a lattice above 4 GiB per population
     buffer keeps the sweeps in the rows layout (per-row buffer resources); switching it to the
     planes layout moves it to the two-pass step, and both sweeps are then refused.  The
-    default below 4 GiB on a large lattice is the two-step sweep (256 x 24); beyond 4 GiB, and
-    on small lattices, the one-step sweep (512 x 8 with two rows in flight and XCD order,
-    narrowed on small lattices)."""
+    default on every lattice is the two-step sweep with 256 threads: 16-row segments where that
+    gives at least 8192 waves (beyond 4 GiB too, in the rows layout), else 24 rows where that
+    gives about 3072, else the height (6 to 24 rows) that gives about 3200 waves."""
     from paper_1412_5170_amd import lbm
     eos, frc, coll = lbm.make_eos(0.5, K=1 / 49), lbm.make_force("GUO_LI", sigma=0.125), \
         lbm.make_collision("MRT")
@@ -192,7 +192,7 @@ def test_launch_rules_beyond_4gib():
     fb = ctypes.c_size_t()
     assert lbm.lbm_layout(big, None, None, ctypes.byref(fb), None) == lbm.LBM_OK
     assert fb.value > 2 ** 32
-    assert launch(big) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
+    assert launch(big) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 256, 16, 0) == lbm.LBM_OK
     assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
     assert launch(big)[0] == lbm.LBM_KERNEL_TWO_PASS
@@ -203,17 +203,21 @@ def test_launch_rules_beyond_4gib():
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(big)
     small = create(4096, 4096)
-    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
     assert lbm.lbm_set_layout(small, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
-    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 24, 0)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
     lbm.lbm_destroy(small)
-    mid = create(1024, 1024)  # too few strips for the two-step sweep to fill the GPU
-    assert launch(mid)[0] == lbm.LBM_KERNEL_SWEEP
-    lbm.lbm_destroy(mid)
+    for n, ty in ((3000, 16), (2048, 24)):  # 52 x 188 = 9776 waves of 16 rows; 36 x 86 = 3096 of 24
+        h = create(n, n)
+        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, 0)
+        lbm.lbm_destroy(h)
+    # smaller lattices: the segment height that gives about 3200 waves, between 6 and 24 rows
+    for n, ty in ((1536, 14), (1024, 6), (512, 6)):
+        h = create(n, n)
+        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, 0)
+        lbm.lbm_destroy(h)
     tiny = create(300, 130)
-    k, tx, ty, _ = launch(tiny)
-    assert k == lbm.LBM_KERNEL_SWEEP and tx <= 512 and ty <= 8
-    assert ((300 + tx - 1) // tx) * ((130 + ty - 1) // ty) >= 64
+    assert launch(tiny) == (lbm.LBM_KERNEL_SWEEP2, 256, 6, 0)
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 320, 32, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(tiny)

@@ -366,6 +366,7 @@ def test_two_step_sweep_is_bitwise_the_one_step_sweep(L, shape):
                 lat.init(rho0)
                 lat.step(steps)
                 one = gpu_lattice(L, wl, PRECISIONS[prec])
+                one.set_launch(L.LBM_KERNEL_SWEEP, 64, 4, L.LBM_LAUNCH_XCD_ORDER)
                 one.init(rho0)
                 one.step(steps)
                 assert np.array_equal(lat.populations(), one.populations()), (tx, ty, steps)
