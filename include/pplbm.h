@@ -273,10 +273,12 @@ void lbm_batch_destroy(lbm_batch_t *b);
  * launches per kind, which the
  * GPU may run side by side; LBM_LAUNCH_SERIAL_KINDS captures them one after another on the
  * batch's stream instead.  LBM_LAUNCH_TWO_STEP advances two steps per launch with the
- * single lattice's two-step sweep (64-lane strips of 58 output columns, 24-row segments; with
+ * single lattice's two-step sweep (64-lane strips of 58 output columns; segments of 6 to 24
+ * rows, chosen at every change of the active set by the single lattice's rule applied to the
+ * active lattices' total wave count; with
  * n = 2 mod 4 steps the last two are one-step launches).  Results are bitwise the same in every
  * case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP (the 64-lattice droplet
- * sweep to equilibrium: 56.8 s against 78.5 s with one step per launch). */
+ * sweep to equilibrium: 56.1 s against 78.5 s with one step per launch). */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 
 /* Segment height (rows per tile) of lattice i; 0 (the default) is automatic: every time the

@@ -40,6 +40,7 @@ struct lbm_batch {
     int4 *tiles2 = nullptr;          // two-step tile list: (lattice, first output column,
     int2 *meta2 = nullptr;           //   first row, rows), and each kind's slice of it
     size_t max_tiles2 = 0;
+    int rows2 = 24;                  // segment height of the two-step tiles, per upload
     std::vector<int> kinds;          // kinds present (scheme * 2 + collision), ascending
     size_t max_tiles = 0;
     // observables
@@ -98,12 +99,31 @@ size_t tiles_max(const lbm_batch *b, int i) {
     return tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : kAutoRowsMin);
 }
 
-constexpr int kTwoStepRows = 24;  // segment height of the two-step tiles
+constexpr int kTwoStepRowsMin = 6;  // lowest segment height of the two-step tiles
 
-size_t tiles2_at(const lbm_batch *b, int i) {
+size_t tiles2_at(const lbm_batch *b, int i, int rows) {
     const Physics &p = b->phys[i];
     const int w = pplbm::sweep2_out_columns();
-    return (size_t)((p.nx + w - 1) / w) * ((p.ny + kTwoStepRows - 1) / kTwoStepRows);
+    return (size_t)((p.nx + w - 1) / w) * ((p.ny + rows - 1) / rows);
+}
+
+// Segment height of the two-step tiles of the active lattices, by the single lattice's rule
+// on the total wave count (the kinds run side by side): 16 rows where that makes at least 8192
+// waves, else 24 where that makes about 3072, else the lowest height from 6 rows up that makes
+// at most about 3200 (one resident round).  As converged lattices leave, the ones still
+// running are cut into shorter segments, so the last few still spread over the GPU.
+int two_step_rows(const lbm_batch *b) {
+    auto count = [&](int rows) {
+        size_t n = 0;
+        for (int i = 0; i < b->count; ++i)
+            if (b->active[i]) n += tiles2_at(b, i, rows);
+        return n;
+    };
+    if (count(16) >= 8192) return 16;
+    if (count(24) >= 3072) return 24;
+    for (int rows = kTwoStepRowsMin; rows < 24; ++rows)
+        if (count(rows) <= 3200) return rows;
+    return 24;
 }
 
 bool two_step(const lbm_batch *b) { return b->flags & LBM_LAUNCH_TWO_STEP; }
@@ -169,7 +189,7 @@ int upload_tiles(lbm_batch *b) {
     std::vector<int2> meta2;
     if (two_step(b)) {
         size_t need2 = 0;
-        for (int i = 0; i < b->count; ++i) need2 += tiles2_at(b, i);
+        for (int i = 0; i < b->count; ++i) need2 += tiles2_at(b, i, kTwoStepRowsMin);
         if (need2 > b->max_tiles2) {
             drop_graph(b);
             if (b->tiles2) (void)hipFree(b->tiles2);
@@ -182,14 +202,15 @@ int upload_tiles(lbm_batch *b) {
             b->max_tiles2 = need2;
         }
         const int w = pplbm::sweep2_out_columns();
+        b->rows2 = two_step_rows(b);
         for (int kind : b->kinds) {
             const int first = (int)t2.size();
             for (int i = 0; i < b->count; ++i) {
                 if (!b->active[i]) continue;
                 const Physics &p = b->phys[i];
                 if (p.scheme * 2 + p.coll != kind) continue;
-                for (int y0 = 0; y0 < p.ny; y0 += kTwoStepRows)
-                    for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(make_int4(i, x0, y0, kTwoStepRows));
+                for (int y0 = 0; y0 < p.ny; y0 += b->rows2)
+                    for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(make_int4(i, x0, y0, b->rows2));
             }
             meta2.push_back(make_int2(first, (int)t2.size() - first));
         }
@@ -216,7 +237,7 @@ int grid_groups(const lbm_batch *b) {
 // Workgroups (of four waves) of a two-step launch: one wave per tile up to 4096 waves.
 int grid2_groups(const lbm_batch *b) {
     size_t all = 0;
-    for (int i = 0; i < b->count; ++i) all += tiles2_at(b, i);
+    for (int i = 0; i < b->count; ++i) all += tiles2_at(b, i, kTwoStepRowsMin);
     return (int)std::max<size_t>(std::min<size_t>((all + 3) / 4, 1024), 1);
 }
 
