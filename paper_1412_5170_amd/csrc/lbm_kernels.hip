@@ -58,15 +58,15 @@ __device__ __forceinline__ T density9(const float f[9]) {
 
 // Effective density of Eq. 7 with the rescaled Carnahan-Starling pressure of Eq. 29-30.
 // NaN when the node is outside the EOS (b rho/4 >= 1) or 2 U / G <= 0.
-// 1 / x for x > 0 from the hardware reciprocal refined by Newton steps (two in FP64, none in
-// FP32): within an ulp or two of the correctly rounded quotient at a fraction of its cost.
+// 1 / x for x > 0 from the hardware reciprocal: in FP32 as it is (1 ulp); in FP64 refined by
+// one Newton step, which squares the estimate's relative error (an estimate good to single
+// precision comes out good to about 2^-46, far below the FP32 rounding of the stored state).
 template <typename T>
 __device__ __forceinline__ T recip(T x) {
     if constexpr (sizeof(T) == 4) {
         return __builtin_amdgcn_rcpf(x);
     } else {
-        T r = __builtin_amdgcn_rcp(x);
-        r = fma(r, fma(-x, r, T(1)), r);
+        const T r = __builtin_amdgcn_rcp(x);
         return fma(r, fma(-x, r, T(1)), r);
     }
 }
@@ -316,8 +316,10 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
     for (int q = 1; q < 9; ++q) fs[q] = (float)((D)f[q] + upd[q]);
     // Every scheme conserves mass exactly (sum_q f*_q = rho); closing the rest population on
     // it keeps the binary rounding of the weights 4/9, 1/9, 1/36 from drifting the mass.
-    fs[0] = (float)(rho_d - density<D>(D(0), (D)fs[1], (D)fs[2], (D)fs[3], (D)fs[4], (D)fs[5],
-                                       (D)fs[6], (D)fs[7], (D)fs[8]));
+    // (density()'s order without its first term)
+    const D moving = (((D)fs[1] + (D)fs[3]) + ((D)fs[2] + (D)fs[4])) +
+                     (((D)fs[5] + (D)fs[7]) + ((D)fs[6] + (D)fs[8]));
+    fs[0] = (float)(rho_d - moving);
 }
 
 __device__ __forceinline__ void put(float *p, float v, bool nt) {
