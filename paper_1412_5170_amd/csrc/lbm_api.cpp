@@ -163,17 +163,20 @@ int maxwell(const lbm_eos &e, double *rho_g, double *rho_l) {
     return LBM_OK;
 }
 
-// One-pass sweep with strips as wide as 512 columns and segments as tall as 8 rows, two rows
-// of loads in flight and XCD-ordered tiles (the fastest measured shape on MRT droplets from
-// 2048^2 to 8192^2), narrowed and shortened (down to 64 x 4) until the launch has about 1024
-// workgroups to spread over the 256 compute units.  lbm_set_launch or lbm_autotune replaces it.
+// Shape of the one-step sweep, which also runs the odd last step of a two-step lbm_step call:
+// strips as wide as 512 columns and segments as tall as 8 rows, two rows of loads in flight
+// and XCD-ordered tiles (its fastest measured shape on MRT droplets from 2048^2 to 8192^2),
+// narrowed and shortened (down to 64 x 4) until the launch has about 1024 workgroups to spread
+// over the 256 compute units.
 pplbm::Launch default_launch(int nx, int ny) {
     pplbm::Launch L;
     L.kernel = pplbm::kKernelSweep;
     L.flags = pplbm::kFlagXCD;
     L.tx = 512;
     L.ty = 8;
-    auto groups = [&]() { return (double)((nx + L.tx - 1) / L.tx) * ((ny + L.ty - 1) / L.ty); };
+    auto groups = [&]() {
+        return (double)(((long long)nx + L.tx - 1) / L.tx) * (((long long)ny + L.ty - 1) / L.ty);
+    };
     while (groups() < 1024 && (L.tx > 64 || L.ty > 4)) {
         if (L.tx > 64 && (L.tx >= 2 * 64 && nx <= L.tx * 4)) L.tx /= 2;
         else if (L.ty > 4) L.ty /= 2;
@@ -371,17 +374,17 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     // sweep).  The one-step sweep's default shape serves the odd last step.
     h->launch = default_launch(nx, ny);
     {
-        const long long strips = (nx + 57) / 58;
+        const long long X = nx, Y = ny, strips = (X + 57) / 58;
         h->launch.kernel = pplbm::kKernelSweep2;
         h->launch.tx = 256;
         h->launch.flags = 0;
-        if (strips * ((ny + 15) / 16) >= 8192) {
+        if (strips * ((Y + 15) / 16) >= 8192) {
             h->launch.ty = 16;
-        } else if (strips * ((ny + 23) / 24) >= 3072) {
+        } else if (strips * ((Y + 23) / 24) >= 3072) {
             h->launch.ty = 24;
         } else {
             const long long segs = std::max(1LL, 3200 / strips);
-            h->launch.ty = (int)std::min(24LL, std::max(6LL, (ny + segs - 1) / segs));
+            h->launch.ty = (int)std::min(24LL, std::max(6LL, (Y + segs - 1) / segs));
         }
     }
     *out = h;
