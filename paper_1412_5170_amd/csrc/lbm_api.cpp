@@ -681,22 +681,29 @@ int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_o
     const int fls[] = {pplbm::kFlagXCD | pplbm::kFlagShallow, pplbm::kFlagShallow,
                        pplbm::kFlagXCD, pplbm::kFlagXCD | pplbm::kFlagShallow | pplbm::kFlagNT};
     const int width = (int)std::min<size_t>(h->p.pitch, 512);
-    for (int tx : txs) {
-        if (tx > 64 && tx > width) continue;  // strips wider than the lattice only idle
-        for (int ty : tys) {
-            if (ty > 8 && ty / 2 >= h->p.ny) continue;
-            for (int fl : fls) {
-                if (he != hipSuccess || rc) break;
-                trial(LBM_KERNEL_SWEEP, tx, ty, fl);
+    if (sweep_fits(h)) {
+        for (int tx : txs) {
+            if (tx > 64 && tx > width) continue;  // strips wider than the lattice only idle
+            for (int ty : tys) {
+                if (ty > 8 && ty / 2 >= h->p.ny) continue;
+                for (int fl : fls) {
+                    if (he != hipSuccess || rc) break;
+                    trial(LBM_KERNEL_SWEEP, tx, ty, fl);
+                }
             }
         }
-    }
-    if (pplbm::pop_bytes(h->p) <= pplbm::kSweepMaxBytes) {  // two steps per launch
-        for (int tx : {64, 128, 256})
-            for (int ty : {16, 32, 48, 64}) {
+        for (int tx : {64, 128, 256})  // two steps per launch
+            for (int ty : {6, 8, 12, 16, 24, 32}) {
                 if (he != hipSuccess || rc) break;
-                if (ty > 16 && ty / 2 >= h->p.ny) continue;
+                if (ty > 6 && ty / 2 >= h->p.ny) continue;
                 trial(LBM_KERNEL_SWEEP2, tx, ty, 0);
+            }
+    } else {  // planes layout beyond 4 GiB: only the two-pass step can run
+        for (int tx : {64, 128, 256})
+            for (int ty : {2, 4, 8}) {
+                if (he != hipSuccess || rc) break;
+                if (tx * ty > 1024) continue;  // threads per workgroup of the fused pass
+                trial(LBM_KERNEL_TWO_PASS, tx, ty, pplbm::kFlagXCD);
             }
     }
     // restore the state whatever happened

@@ -42,7 +42,7 @@ def test_single_autotune_restores_state_and_caches(L, tmp_path):
     assert a.stats()["step"] == 10
     k, tx, ty, fl = a.get_launch()
     assert ((k == L.LBM_KERNEL_SWEEP and tx in (64, 128, 256, 512) and ty in (4, 8, 16, 32, 64))
-            or (k == L.LBM_KERNEL_SWEEP2 and tx in (64, 128, 256) and ty in (16, 32, 48, 64)))
+            or (k == L.LBM_KERNEL_SWEEP2 and tx in (64, 128, 256) and ty in (6, 8, 12, 16, 24, 32)))
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     rec = json.loads(lines[0])
@@ -55,6 +55,30 @@ def test_single_autotune_restores_state_and_caches(L, tmp_path):
     assert c.autotune(str(cache), trial_steps=4) == -1.0
     assert c.get_launch() == (k, tx, ty, fl)
     assert len(cache.read_text().splitlines()) == 1
+
+
+def test_autotune_planes_beyond_4gib_times_two_pass_shapes(L):
+    """A planes-layout lattice beyond 4 GiB per population buffer runs only the two-pass step:
+    the autotuner times two-pass shapes there and keeps one of them, and the step count is
+    left as it was."""
+    import torch
+    n = 10944  # 9 x 4 x 10944^2 B = 4.31 GB per buffer
+    say(f"autotune planes {n}x{n}")
+    lat = L.Lattice(n, n, L.make_eos(0.6, K=1 / 49), L.make_force("GUO_LI", sigma=0.125),
+                    L.make_collision("MRT"), 0.9, layout=L.LBM_LAYOUT_PLANES)
+    assert lat.get_launch()[0] == L.LBM_KERNEL_TWO_PASS
+    g, l, _ = TH.maxwell(0.6)
+    rho0 = np.full((n, n), l)  # uniform: stays uniform, no interface to resolve
+    lat.init(rho0)
+    del rho0
+    lat.step(2)
+    assert lat.autotune(None, trial_steps=2) > 0
+    k, tx, ty, fl = lat.get_launch()
+    assert k == L.LBM_KERNEL_TWO_PASS and tx in (64, 128, 256) and ty in (2, 4, 8)
+    assert fl == L.LBM_LAUNCH_XCD_ORDER
+    assert lat.stats()["step"] == 2
+    del lat
+    torch.cuda.empty_cache()
 
 
 def test_batch_autotune_restores_state(L, tmp_path):
