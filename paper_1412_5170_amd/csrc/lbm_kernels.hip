@@ -699,11 +699,14 @@ sweep_kernel_w5(const float *__restrict__ fin, float *__restrict__ fout, StepCon
 // columns and neighbouring strips overlap by 6.  Same per-node arithmetic as the one-step
 // sweep, so the same bits.
 // ---------------------------------------------------------------------------------------
+// Whole-wave shifts by one lane.  The end lane with no source reads 0 through the bound
+// control bit, so no old value has to be written into the destination first (one move less
+// per shift); that lane lies outside the valid range either way.
 __device__ __forceinline__ float lane_below(float v) {  // lane i receives lane i - 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_above(float v) {  // lane i receives lane i + 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 constexpr int kSweep2Out = 58;  // output columns of a 64-lane strip (lanes 3..60)
