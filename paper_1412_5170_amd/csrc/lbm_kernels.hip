@@ -56,8 +56,6 @@ __device__ __forceinline__ T density9(const float f[9]) {
     return density<T>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
 }
 
-// Effective density of Eq. 7 with the rescaled Carnahan-Starling pressure of Eq. 29-30.
-// NaN when the node is outside the EOS (b rho/4 >= 1) or 2 U / G <= 0.
 // 1 / x for x > 0 from the hardware reciprocal: in FP32 as it is (1 ulp); in FP64 refined by
 // one Newton step, which squares the estimate's relative error (an estimate good to single
 // precision comes out good to about 2^-46, far below the FP32 rounding of the stored state).
@@ -71,17 +69,21 @@ __device__ __forceinline__ T recip(T x) {
     }
 }
 
+// Effective density of Eq. 7 with the rescaled Carnahan-Starling pressure of Eq. 29-30,
+// p0 = K rho (R T Z - a rho), Z = (1 + eta + eta^2 - eta^3) / (1 - eta)^3, eta = b rho / 4.
+// The radicand 2 (p0 - rho/3) / G is formed as rho (e1 Z - (e2 rho + e3)) with the constants
+// e1 = 2 K R T / G, e2 = 2 K a / G, e3 = 2 / (3 G) folded on the host.  NaN when the node is
+// outside the EOS (b rho/4 >= 1, rho <= 0) or 2 U / G <= 0.
 template <typename T>
-__device__ __forceinline__ T eos_psi(T rho, T bq, T RT, T a, T K, T two_over_G) {
+__device__ __forceinline__ T eos_psi(T rho, T bq, T e1, T e2, T e3) {
     const T eta = bq * rho;
-    if (!(eta < T(1)) || !(rho > T(0))) return qnan<T>();
     const T om = T(1) - eta;
-    const T Z = (T(1) + eta * (T(1) + eta * (T(1) - eta))) * recip<T>(om * om * om);
-    const T p0 = K * (rho * (RT * Z - a * rho));
-    const T r = two_over_G * (p0 - rho * (T(1) / T(3)));
+    const T Z = (T(1) + eta * (T(1) + eta * om)) * recip<T>(om * om * om);
+    const T r = rho * (e1 * Z - (e2 * rho + e3));
     // psi is stored in FP32, so its square root is the hardware FP32 one (1 ulp) of the
     // radicand rounded once.
-    return r > T(0) ? T(__builtin_amdgcn_sqrtf((float)r)) : qnan<T>();
+    const bool ok = eta < T(1) && rho > T(0) && r > T(0);
+    return ok ? T(__builtin_amdgcn_sqrtf((float)r)) : qnan<T>();
 }
 
 // Effective density of Eq. 33 (Sbragaglia-Shan): exp(-1/rho) for eps = 0 (inv_eps = 0 flags
@@ -104,7 +106,7 @@ struct StepConst {
     unsigned fbytes;   // bytes of one population buffer when below 4 GiB (whole-buffer resource)
     size_t ffloats;    // floats of one population buffer (per-row resources beyond 4 GiB)
     int flags;         // kFlagNT | kFlagXCD
-    D bq, RT, a, K, two_over_G;  // EOS (Eq. 29-30) and Eq. 7
+    D bq, e1, e2, e3;  // EOS (Eq. 29-30) through Eq. 7: b/4 and the constants of eos_psi
     int psi_kind;     // 0: psi from the C-S EOS through Eq. 7; 1: psi of Eq. 33
     D inv_eps;        // Eq. 33 exponent 1/eps (0: the exp(-1/rho) branch)
     D tau;            // relaxation time (Shan-Chen velocity shift, Eq. 21)
@@ -119,7 +121,7 @@ struct StepConst {
     R lim[9]; // 1 / (1/s_k - 1/2) for the moments that carry Li's stress
 
     __device__ __forceinline__ float psi_of_rho(D rho) const {
-        if (psi_kind == 0) return (float)eos_psi<D>(rho, bq, RT, a, K, two_over_G);
+        if (psi_kind == 0) return (float)eos_psi<D>(rho, bq, e1, e2, e3);
         // Eq. 33 in the shape precision R (FP32 in the mixed path): psi is stored in FP32.
         return (float)ss_psi<R>((R)rho, (R)inv_eps);
     }
@@ -1244,10 +1246,9 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.ffloats = pop_bytes(p) / sizeof(float);
     c.flags = flags;
     c.bq = (D)p.b_quarter;
-    c.RT = (D)p.RT;
-    c.a = (D)p.a;
-    c.K = (D)p.K;
-    c.two_over_G = (D)(2.0 / p.G);
+    c.e1 = (D)(2.0 * p.K * p.RT / p.G);
+    c.e2 = (D)(2.0 * p.K * p.a / p.G);
+    c.e3 = (D)(2.0 / (3.0 * p.G));
     c.psi_kind = p.psi_kind;
     c.inv_eps = (D)p.inv_eps;
     c.tau = (D)p.tau;
