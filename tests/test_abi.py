@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -221,3 +222,35 @@ def test_launch_rules_beyond_4gib():
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 320, 32, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(tiny)
+
+
+def test_default_two_step_heights_follow_the_wave_count():
+    """The default segment height of the two-step sweep, on many lattice shapes (host rule, no
+    GPU call): 16 rows where that makes at least 8192 waves of 58 columns, else 24 rows where
+    that makes at least 3072, else the lowest height from 6 to 24 rows that keeps the wave count
+    at or below about 3200 (one resident round)."""
+    from paper_1412_5170_amd import lbm
+    eos, frc, coll = lbm.make_eos(0.6, K=1 / 49), lbm.make_force("GUO_LI", sigma=0.125), \
+        lbm.make_collision("BGK")
+    rng = np.random.default_rng(7)
+    shapes = [(1, 1), (3, 3), (4, 256), (58, 58), (59, 7), (4096, 8), (8, 4096), (100000, 4)]
+    shapes += [tuple(int(v) for v in rng.integers(1, 6000, 2)) for _ in range(40)]
+    for nx, ny in shapes:
+        h = lbm._P()
+        assert lbm.lbm_create(nx, ny, ctypes.byref(eos), ctypes.byref(frc), ctypes.byref(coll),
+                              0.9, ctypes.byref(h)) == lbm.LBM_OK
+        v = [ctypes.c_int() for _ in range(4)]
+        assert lbm.lbm_get_launch(h, *[ctypes.byref(x) for x in v]) == lbm.LBM_OK
+        k, tx, ty, fl = (x.value for x in v)
+        lbm.lbm_destroy(h)
+        strips = -(-nx // 58)
+        waves = lambda rows: strips * -(-ny // rows)  # noqa: E731
+        assert (k, tx, fl) == (lbm.LBM_KERNEL_SWEEP2, 256, 0), (nx, ny)
+        if waves(16) >= 8192:
+            assert ty == 16, (nx, ny, ty)
+        elif waves(24) >= 3072:
+            assert ty == 24, (nx, ny, ty)
+        else:
+            assert 6 <= ty <= 24, (nx, ny, ty)
+            assert ty == 6 or waves(ty) <= 3200, (nx, ny, ty)
+            assert ty == 6 or waves(ty - 1) > 3200, (nx, ny, ty)
