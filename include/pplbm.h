@@ -156,8 +156,8 @@ int lbm_set_layout(lbm_t *h, int layout);
 int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
 
 /* Kernel shape of lbm_step.  Every choice computes bitwise the same result.  The default is
- * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, flags 0) on every lattice, with S =
- * ceil(nx / 58) strips: ty = 16 where S * ceil(ny / 16) >= 8192 (from about 3000^2), else
+ * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, LBM_LAUNCH_XCD_ORDER) on every lattice,
+ * with S = ceil(nx / 58) strips: ty = 16 where S * ceil(ny / 16) >= 8192 (from about 3000^2), else
  * ty = 24 where S * ceil(ny / 24) >= 3072 (about 2048^2), else the ty between 6 and 24 that
  * gives about 3200 waves.  The odd last step of an lbm_step call runs the one-step sweep with
  * tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then
@@ -181,7 +181,7 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  *     multiple of 64, <= 256).  An odd last step of lbm_step runs the one-step sweep.  Beyond
  *     4 GiB of populations it addresses rows like the one-step sweep (rows layout only).
  * flags: LBM_LAUNCH_NONTEMPORAL (non-temporal stores of the new populations),
- *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD),
+ *        LBM_LAUNCH_XCD_ORDER (consecutive tiles on the same XCD; both sweeps),
  *        LBM_LAUNCH_SHALLOW (sweep only: load one row ahead instead of two; fewer registers). */
 enum { LBM_KERNEL_TWO_PASS = 0, LBM_KERNEL_SWEEP = 1, LBM_KERNEL_SWEEP2 = 2 };
 #define LBM_LAUNCH_NONTEMPORAL 1
@@ -230,7 +230,7 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 /* Autotuner: times trial_steps steps (rounded up to even) of the one-pass sweep for strip widths
  * tx in {64, 128, 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets
  * XCD|SHALLOW, SHALLOW, XCD, XCD|SHALLOW|NONTEMPORAL, and of the two-step sweep for tx in
- * {64, 128, 256} and ty in {6, 8, 12, 16, 24, 32}; a planes-layout lattice beyond 4 GiB, where
+ * {64, 128, 256}, ty in {6, 8, 12, 16, 24, 32} and the flags XCD or none; a planes-layout lattice beyond 4 GiB, where
  * neither sweep runs, tries the two-pass step for tx in {64, 128, 256} and ty in {2, 4, 8}
  * (tx * ty <= 1024) with LBM_LAUNCH_XCD_ORDER (shapes are bitwise equivalent, so only speed differs).  Keeps the
  * fastest and applies it with lbm_set_launch.  Runs on the current state, which it saves and

@@ -377,7 +377,7 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
         const long long X = nx, Y = ny, strips = (X + 57) / 58;
         h->launch.kernel = pplbm::kKernelSweep2;
         h->launch.tx = 256;
-        h->launch.flags = 0;
+        h->launch.flags = pplbm::kFlagXCD;  // 4096^2: 167.8 -> 159.2 us per step
         if (strips * ((Y + 15) / 16) >= 8192) {
             h->launch.ty = 16;
         } else if (strips * ((Y + 23) / 24) >= 3072) {
@@ -693,11 +693,12 @@ int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_o
             }
         }
         for (int tx : {64, 128, 256})  // two steps per launch
-            for (int ty : {6, 8, 12, 16, 24, 32}) {
-                if (he != hipSuccess || rc) break;
-                if (ty > 6 && ty / 2 >= h->p.ny) continue;
-                trial(LBM_KERNEL_SWEEP2, tx, ty, 0);
-            }
+            for (int ty : {6, 8, 12, 16, 24, 32})
+                for (int fl : {pplbm::kFlagXCD, 0}) {
+                    if (he != hipSuccess || rc) break;
+                    if (ty > 6 && ty / 2 >= h->p.ny) continue;
+                    trial(LBM_KERNEL_SWEEP2, tx, ty, fl);
+                }
     } else {  // planes layout beyond 4 GiB: only the two-pass step can run
         for (int tx : {64, 128, 256})
             for (int ty : {2, 4, 8}) {

@@ -820,8 +820,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
               int nstrips, int ntiles) {
     // the wave's tile: uniform across the wave (a scalar), so that row offsets stay scalar
-    // operands of the buffer accesses
-    const int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // operands of the buffer accesses; with LBM_LAUNCH_XCD_ORDER consecutive workgroups (rows
+    // of strips, and the segments above and below them) share one XCD's L2
+    const int b = tile_id(blockIdx.x, gridDim.x, c.flags & kFlagXCD);
+    const int t = b * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= ntiles) return;  // whole waves
     sweep2_tile<R, D, SCHEME, COLL, BIG>(fin, fout, c, (t % nstrips) * kSweep2Out,
                                          (t / nstrips) * H, H);

@@ -171,7 +171,7 @@ def test_launch_rules_beyond_4gib():
     """Host-side launch rules (no GPU call is made): a lattice above 4 GiB per population
     buffer keeps the sweeps in the rows layout (per-row buffer resources); switching it to the
     planes layout moves it to the two-pass step, and both sweeps are then refused.  The
-    default on every lattice is the two-step sweep with 256 threads: 16-row segments where that
+    default on every lattice is the two-step sweep with 256 threads in XCD order: 16-row segments where that
     gives at least 8192 waves (beyond 4 GiB too, in the rows layout), else 24 rows where that
     gives about 3072, else the height (6 to 24 rows) that gives about 3200 waves."""
     from paper_1412_5170_amd import lbm
@@ -193,7 +193,7 @@ def test_launch_rules_beyond_4gib():
     fb = ctypes.c_size_t()
     assert lbm.lbm_layout(big, None, None, ctypes.byref(fb), None) == lbm.LBM_OK
     assert fb.value > 2 ** 32
-    assert launch(big) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
+    assert launch(big) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, lbm.LBM_LAUNCH_XCD_ORDER)
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP, 256, 16, 0) == lbm.LBM_OK
     assert lbm.lbm_set_layout(big, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
     assert launch(big)[0] == lbm.LBM_KERNEL_TWO_PASS
@@ -204,21 +204,21 @@ def test_launch_rules_beyond_4gib():
     assert lbm.lbm_set_launch(big, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(big)
     small = create(4096, 4096)
-    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, lbm.LBM_LAUNCH_XCD_ORDER)
     assert lbm.lbm_set_layout(small, lbm.LBM_LAYOUT_PLANES) == lbm.LBM_OK
-    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, 0)
+    assert launch(small) == (lbm.LBM_KERNEL_SWEEP2, 256, 16, lbm.LBM_LAUNCH_XCD_ORDER)
     lbm.lbm_destroy(small)
     for n, ty in ((3000, 16), (2048, 24)):  # 52 x 188 = 9776 waves of 16 rows; 36 x 86 = 3096 of 24
         h = create(n, n)
-        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, 0)
+        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, lbm.LBM_LAUNCH_XCD_ORDER)
         lbm.lbm_destroy(h)
     # smaller lattices: the segment height that gives about 3200 waves, between 6 and 24 rows
     for n, ty in ((1536, 14), (1024, 6), (512, 6)):
         h = create(n, n)
-        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, 0)
+        assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, lbm.LBM_LAUNCH_XCD_ORDER)
         lbm.lbm_destroy(h)
     tiny = create(300, 130)
-    assert launch(tiny) == (lbm.LBM_KERNEL_SWEEP2, 256, 6, 0)
+    assert launch(tiny) == (lbm.LBM_KERNEL_SWEEP2, 256, 6, lbm.LBM_LAUNCH_XCD_ORDER)
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 320, 32, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
     lbm.lbm_destroy(tiny)
@@ -245,7 +245,7 @@ def test_default_two_step_heights_follow_the_wave_count():
         lbm.lbm_destroy(h)
         strips = -(-nx // 58)
         waves = lambda rows: strips * -(-ny // rows)  # noqa: E731
-        assert (k, tx, fl) == (lbm.LBM_KERNEL_SWEEP2, 256, 0), (nx, ny)
+        assert (k, tx, fl) == (lbm.LBM_KERNEL_SWEEP2, 256, lbm.LBM_LAUNCH_XCD_ORDER), (nx, ny)
         if waves(16) >= 8192:
             assert ty == 16, (nx, ny, ty)
         elif waves(24) >= 3072:
