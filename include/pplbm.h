@@ -280,7 +280,7 @@ void lbm_batch_destroy(lbm_batch_t *b);
  * active lattices' total wave count; with
  * n = 2 mod 4 steps the last two are one-step launches).  Results are bitwise the same in every
  * case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP (the 64-lattice droplet
- * sweep to equilibrium: 54.7 s against 78.5 s with one step per launch). */
+ * sweep to equilibrium: 54.5 s against 78.5 s with one step per launch). */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 
 /* Segment height (rows per tile) of lattice i; 0 (the default) is automatic: every time the

@@ -234,11 +234,13 @@ int grid_groups(const lbm_batch *b) {
     return (int)g;
 }
 
-// Workgroups (of four waves) of a two-step launch: one wave per tile up to 4096 waves.
+// Workgroups (of four waves) of a two-step launch: one wave per tile up to 4096 waves, a
+// multiple of 8 (each XCD walks its own eighth of the tile list).
 int grid2_groups(const lbm_batch *b) {
     size_t all = 0;
     for (int i = 0; i < b->count; ++i) all += tiles2_at(b, i, kTwoStepRowsMin);
-    return (int)std::max<size_t>(std::min<size_t>((all + 3) / 4, 1024), 1);
+    const size_t g = std::min<size_t>((all + 3) / 4, 1024);
+    return (int)std::max<size_t>((g + 7) / 8 * 8, 8);
 }
 
 // n (even) steps as launches: with two steps per launch, 2 (n / 4) two-step launches and the

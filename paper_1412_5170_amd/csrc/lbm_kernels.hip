@@ -869,17 +869,23 @@ batch_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict_
     }
 }
 
-// Two steps per launch for one kind of the batch: every wave walks the kind's slice meta2[kind]
+// Two steps per launch for one kind of the batch: the waves walk the kind's slice meta2[kind]
 // of the two-step tile list (lattice, first output column, first row, rows), one 64-lane strip
 // of 58 output columns per tile (the single lattice's two-step sweep, tile by tile).
+// Workgroups are dealt round-robin to the eight XCDs (the grid is a multiple of 8): the waves
+// of XCD k walk the k-th eighth of the slice, so tiles that overlap (neighbouring strips and
+// segments of one lattice) are read through the same L2.
 template <int SCHEME, int COLL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 batch2_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict__ tiles,
                    const int2 *__restrict__ meta, int kind, int parity) {
     const int2 m = meta[kind];
-    const int waves = gridDim.x * (blockDim.x >> 6);
-    const int w = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int t = w; t < m.y; t += waves) {
+    const int wpg = blockDim.x >> 6;
+    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int begin = (int)((long long)m.y * xcd / 8), end = (int)((long long)m.y * (xcd + 1) / 8);
+    const int waves = per * wpg;
+    const int w = local * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int t = begin + w; t < end; t += waves) {
         const int4 tl = tiles[m.x + t];
         const BatchLattice &L = lats[tl.x];
         const StepConst<float, double> c = L.c;
