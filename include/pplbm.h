@@ -230,10 +230,11 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 /* Autotuner: times trial_steps steps (rounded up to even) of the one-pass sweep for strip widths
  * tx in {64, 128, 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets
  * XCD|SHALLOW, SHALLOW, XCD, XCD|SHALLOW|NONTEMPORAL, and of the two-step sweep for tx in
- * {64, 128, 256}, ty in {6, 8, 12, 16, 24, 32} and the flags XCD or none; a planes-layout lattice beyond 4 GiB, where
- * neither sweep runs, tries the two-pass step for tx in {64, 128, 256} and ty in {2, 4, 8}
- * (tx * ty <= 1024) with LBM_LAUNCH_XCD_ORDER (shapes are bitwise equivalent, so only speed differs).  Keeps the
- * fastest and applies it with lbm_set_launch.  Runs on the current state, which it saves and
+ * {64, 128, 256}, ty in {6, 8, 12, 16, 24, 32} and the flags XCD or none; a planes-layout
+ * lattice beyond 4 GiB, where neither sweep runs, tries the two-pass step for tx in
+ * {64, 128, 256} and ty in {2, 4, 8} (tx * ty <= 1024) with LBM_LAUNCH_XCD_ORDER.  Shapes are
+ * bitwise equivalent, so only speed differs.  Keeps the fastest and applies it with
+ * lbm_set_launch.  Runs on the current state, which it saves and
  * restores (populations and step count), so the simulation resumes exactly where it was.
  * cache_path (may be NULL): JSON lines keyed by device, size, scheme, collision, precision and
  * layout; a hit applies the cached launch without trials (*ms_out = -1).  *ms_out (may be
