@@ -348,7 +348,8 @@ def test_two_step_sweep_is_bitwise_the_one_step_sweep(L, shape):
     """Two time steps per launch (wave strips of 58 output columns, step t+1 two rows behind
     step t, x-neighbours by lane shifts) against the one-step sweep: the same populations bit
     for bit after even and odd step counts, for ragged and tiny lattices, several workgroup
-    sizes and segment heights, three forcing/collision pairs and every precision."""
+    sizes and segment heights, dispatch and XCD order, three forcing/collision pairs and every
+    precision."""
     nx, ny = shape
     for scheme, coll in (("GUO_LI", "MRT"), ("EDM", "BGK"), ("SC", "BGK")):
         wl = workload("droplet_4096_mrt", nx=nx, ny=ny, R=max(1.0, min(nx, ny) / 4),
@@ -359,14 +360,15 @@ def test_two_step_sweep_is_bitwise_the_one_step_sweep(L, shape):
         for prec in precs:
             ref = gpu_lattice(L, wl, PRECISIONS[prec])
             ref.init(rho0)
-            for tx, ty, steps in ((64, 1, 6), (256, 5, 7), (128, 32, 10)):
-                say(f"[two-step sweep] {nx}x{ny} {scheme}/{coll} {prec} tx {tx} ty {ty} {steps}")
+            for tx, ty, fl, steps in ((64, 1, 0, 6), (256, 5, L.LBM_LAUNCH_XCD_ORDER, 7),
+                                      (128, 32, 0, 10)):
+                say(f"[two-step sweep] {nx}x{ny} {scheme}/{coll} {prec} tx {tx} ty {ty} fl {fl} {steps}")
                 lat = gpu_lattice(L, wl, PRECISIONS[prec])
-                lat.set_launch(L.LBM_KERNEL_SWEEP2, tx, ty, 0)
+                lat.set_launch(L.LBM_KERNEL_SWEEP2, tx, ty, fl)
                 lat.init(rho0)
                 lat.step(steps)
                 one = gpu_lattice(L, wl, PRECISIONS[prec])
                 one.set_launch(L.LBM_KERNEL_SWEEP, 64, 4, L.LBM_LAUNCH_XCD_ORDER)
                 one.init(rho0)
                 one.step(steps)
-                assert np.array_equal(lat.populations(), one.populations()), (tx, ty, steps)
+                assert np.array_equal(lat.populations(), one.populations()), (tx, ty, fl, steps)
