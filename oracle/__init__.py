@@ -74,6 +74,7 @@ def lib():
         _lib.orc_psi.argtypes = [pp, ctypes.c_double]
         _lib.orc_psi.restype = ctypes.c_double
         _lib.orc_mrt_matrix.argtypes = [dp, dp]
+        _lib.orc_guo_bracket.argtypes = [ctypes.c_double] * 4 + [dp]
         _lib.orc_threads.restype = ctypes.c_int
     return _lib
 
@@ -191,6 +192,13 @@ def mrt_matrix():
     Minv = np.empty((9, 9))
     _check(lib().orc_mrt_matrix(_ptr(M), _ptr(Minv)))
     return M, Minv
+
+
+def guo_bracket(Fx: float, Fy: float, Vx: float, Vy: float) -> np.ndarray:
+    """Guo's bracket B_a(F, V) of Eq. 23 (without the 1 - 1/(2 tau) factor), nine values."""
+    out = np.empty(9)
+    lib().orc_guo_bracket(Fx, Fy, Vx, Vy, _ptr(out))
+    return out
 
 
 def stats(p: Params, f: np.ndarray, probes=None) -> dict:

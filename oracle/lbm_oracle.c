@@ -452,6 +452,12 @@ int orc_mrt_matrix(double *M_out, double *Minv_out)
     return ORC_OK;
 }
 
+/* Guo's bracket of Eq. 23 at one (F, V), without the (1 - 1/(2 tau)) factor (for tests). */
+void orc_guo_bracket(double Fx, double Fy, double Vx, double Vy, double *out)
+{
+    guo_bracket(Fx, Fy, Vx, Vy, out);
+}
+
 /* Number of OpenMP threads the stepper's parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
