@@ -436,8 +436,9 @@ int lbm_set_stream(lbm_t *h, void *stream) {
 
 int lbm_set_precision(lbm_t *h, int precision) {
     if (!h) return LBM_EINVAL;
-    if (precision != LBM_PREC_F32 && precision != LBM_PREC_F64 && precision != LBM_PREC_MIXED)
-        return fail(h, LBM_EINVAL, "precision must be LBM_PREC_F32, LBM_PREC_F64 or LBM_PREC_MIXED");
+    if (precision != LBM_PREC_F64 && precision != LBM_PREC_MIXED)
+        return fail(h, LBM_EINVAL, "precision must be LBM_PREC_MIXED or LBM_PREC_F64 (FP32 "
+                                   "arithmetic throughout misses 1e-5 after 100 steps and is not offered)");
     h->prec = precision;
     return LBM_OK;
 }

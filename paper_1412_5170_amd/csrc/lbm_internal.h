@@ -35,7 +35,7 @@ struct Physics {
     int scheme, coll;
 };
 
-enum { kPrecF32 = 0, kPrecF64 = 1, kPrecMixed = 2 };
+enum { kPrecF64 = 1, kPrecMixed = 2 };  // the values of LBM_PREC_*
 constexpr int kFlagNT = 1;   // non-temporal stores of the new populations
 constexpr int kFlagXCD = 2;  // XCD-aware order of the tiles
 constexpr int kFlagShallow = 4;  // sweep: prefetch one row ahead instead of two

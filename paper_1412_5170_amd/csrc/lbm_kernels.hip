@@ -1366,7 +1366,6 @@ hipError_t sweep_dispatch(const Physics &p, const Launch &L, const float *fin, f
 hipError_t launch_psi(const Physics &p, int prec, int flags, const float *f, float *psi,
                       hipStream_t s) {
     switch (prec) {
-    case kPrecF32: return psi_dispatch<float, float>(p, flags, f, psi, s);
     case kPrecF64: return psi_dispatch<double, double>(p, flags, f, psi, s);
     default: return psi_dispatch<float, double>(p, flags, f, psi, s);
     }
@@ -1375,7 +1374,6 @@ hipError_t launch_psi(const Physics &p, int prec, int flags, const float *f, flo
 hipError_t launch_fused(const Physics &p, int prec, const Launch &L, const float *fin,
                         const float *psi, float *fout, hipStream_t s) {
     switch (prec) {
-    case kPrecF32: return fused_dispatch<float, float>(p, L, fin, psi, fout, s);
     case kPrecF64: return fused_dispatch<double, double>(p, L, fin, psi, fout, s);
     default: return fused_dispatch<float, double>(p, L, fin, psi, fout, s);
     }
@@ -1405,7 +1403,6 @@ hipError_t sweep2_dispatch(const Physics &p, const Launch &L, const float *fin, 
 hipError_t launch_sweep2(const Physics &p, int prec, const Launch &L, const float *fin,
                          float *fout, hipStream_t s) {
     switch (prec) {
-    case kPrecF32: return sweep2_dispatch<float, float>(p, L, fin, fout, s);
     case kPrecF64: return sweep2_dispatch<double, double>(p, L, fin, fout, s);
     default: return sweep2_dispatch<float, double>(p, L, fin, fout, s);
     }
@@ -1414,7 +1411,6 @@ hipError_t launch_sweep2(const Physics &p, int prec, const Launch &L, const floa
 hipError_t launch_sweep(const Physics &p, int prec, const Launch &L, const float *fin,
                         float *fout, hipStream_t s) {
     switch (prec) {
-    case kPrecF32: return sweep_dispatch<float, float>(p, L, fin, fout, s);
     case kPrecF64: return sweep_dispatch<double, double>(p, L, fin, fout, s);
     default: return sweep_dispatch<float, double>(p, L, fin, fout, s);
     }

@@ -21,7 +21,7 @@ LBM_EOS_CARNAHAN_STARLING, LBM_EOS_SBRAGAGLIA_SHAN = 0, 1
 LBM_FORCE_EDM, LBM_FORCE_GUO, LBM_FORCE_GUO_LI, LBM_FORCE_SC = 0, 1, 2, 3
 LBM_COEX_MAXWELL, LBM_COEX_MECHANICAL = 0, 1
 LBM_COLL_BGK, LBM_COLL_MRT = 0, 1
-LBM_PREC_F32, LBM_PREC_F64, LBM_PREC_MIXED = 0, 1, 2
+LBM_PREC_F64, LBM_PREC_MIXED = 1, 2
 LBM_LAYOUT_PLANES, LBM_LAYOUT_ROWS = 0, 1
 LBM_KERNEL_TWO_PASS, LBM_KERNEL_SWEEP, LBM_KERNEL_SWEEP2 = 0, 1, 2
 LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_XCD_ORDER, LBM_LAUNCH_SHALLOW = 1, 2, 4

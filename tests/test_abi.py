@@ -75,6 +75,9 @@ def test_create_validates(L):
     assert L.lbm_set_tile(h, 48, 4) == L.LBM_EINVAL and L.lbm_set_tile(h, 128, 8) == 0
     assert L.lbm_set_probes(h, 3, 0, 0, 0) == L.LBM_EINVAL
     assert L.lbm_set_precision(h, 7) == L.LBM_EINVAL
+    # FP32 arithmetic throughout (the value 0) misses the 1e-5 bar and is not offered
+    assert L.lbm_set_precision(h, 0) == L.LBM_EINVAL and b"1e-5" in L.lbm_last_error(h)
+    assert L.lbm_set_precision(h, L.LBM_PREC_F64) == 0 and L.lbm_set_precision(h, L.LBM_PREC_MIXED) == 0
     # stepping before init is an ordering error, reported without touching the GPU
     assert L.lbm_step(h, 1) == L.LBM_ESTATE
     assert b"init" in L.lbm_last_error(h)
