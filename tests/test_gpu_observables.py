@@ -1,0 +1,172 @@
+"""The FP64 observables and the batched sweep against the oracle.
+
+* lbm_stats and lbm_batch_stats (mass, min/max density, the probe densities and their ratio,
+  Us_max = max |v|, and the velocity change between two checks -- the quantities of Sec. 4's
+  Tables 3-7 and the convergence rule) against the oracle's definitions evaluated on the same
+  populations, and against the oracle's own trajectory at the parity bar.
+* Every member of a batch -- four forcing/collision kinds, uneven sizes down to 3 x 5, one member
+  dropped and re-activated mid-run -- against the oracle's step, element by element.
+
+Bar (as the other parity tests): 1e-5 relative in rho pointwise and in v norm-wise
+(max |dv| / max |v_ref|)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from lbm_cases import errors, gpu_lattice, initial_density, oracle_params, say, workload
+from oracle import thermo as TH
+from paper_1412_5170_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_5170_amd import lbm
+    return lbm
+
+
+def _oracle_observables(p, f, probes, f_prev=None):
+    """The observables of one state from the oracle's fields (FP64): the probe ratio is the
+    larger probe density over the smaller; dv is max over nodes of max(|dvx|, |dvy|)."""
+    st = O.stats(p, np.ascontiguousarray(f, dtype=np.float64), probes=probes)
+    a, b = st["a"], st["b"]
+    st["ratio"] = max(a, b) / min(a, b)
+    if f_prev is not None:
+        f1 = O.fields(p, np.ascontiguousarray(f_prev, dtype=np.float64))
+        f2 = O.fields(p, np.ascontiguousarray(f, dtype=np.float64))
+        st["dv"] = float(max(np.abs(f2["vx"] - f1["vx"]).max(), np.abs(f2["vy"] - f1["vy"]).max()))
+    return st
+
+
+def _check_same_state(gpu, ref, label):
+    """lbm_stats against the oracle on the very populations the GPU holds: the same sums and
+    extrema (FP64 either side); v differs only by the FP32 rounding of psi in the library's
+    read-out, and the stored previous velocity is FP32."""
+    say(f"    {label}: mass {gpu['mass']:.12e} / {ref['mass']:.12e}, us_max {gpu['us_max']:.6e} / "
+        f"{ref['us_max']:.6e}, ratio {gpu['ratio']:.9f} / {ref['ratio']:.9f}")
+    assert gpu["mass"] == pytest.approx(ref["mass"], rel=1e-12)
+    assert gpu["rho_min"] == pytest.approx(ref["rho_min"], rel=1e-15)
+    assert gpu["rho_max"] == pytest.approx(ref["rho_max"], rel=1e-15)
+    assert gpu["rho_probe_a"] == pytest.approx(ref["a"], rel=1e-15)
+    assert gpu["rho_probe_b"] == pytest.approx(ref["b"], rel=1e-15)
+    assert gpu["ratio"] == pytest.approx(ref["ratio"], rel=1e-14)
+    assert abs(gpu["us_max"] - ref["us_max"]) <= 1e-6 * ref["us_max"]
+    if "dv" in ref:
+        assert abs(gpu["dv_max"] - ref["dv"]) <= 1e-6 * ref["us_max"], (gpu["dv_max"], ref["dv"])
+    assert gpu["nonfinite"] == 0
+
+
+def _check_trajectory(gpu, ref, label):
+    """lbm_stats of the GPU's state against the oracle's own trajectory: the parity bar."""
+    say(f"    {label} vs the oracle's trajectory: mass {abs(gpu['mass'] / ref['mass'] - 1):.2e}, "
+        f"rho_min {abs(gpu['rho_min'] / ref['rho_min'] - 1):.2e}, "
+        f"us_max {abs(gpu['us_max'] - ref['us_max']) / ref['us_max']:.2e}")
+    assert gpu["mass"] == pytest.approx(ref["mass"], rel=1e-6)
+    for k, r in (("rho_min", "rho_min"), ("rho_max", "rho_max"), ("rho_probe_a", "a"),
+                 ("rho_probe_b", "b"), ("ratio", "ratio")):
+        assert gpu[k] == pytest.approx(ref[r], rel=2 * TOL if k == "ratio" else TOL), k
+    assert abs(gpu["us_max"] - ref["us_max"]) <= TOL * ref["us_max"]
+    if "dv" in ref:
+        assert abs(gpu["dv_max"] - ref["dv"]) <= 2 * TOL * ref["us_max"]
+
+
+def test_lbm_stats_against_oracle(L):
+    """The timed workload's physics (MRT, Guo + Li, T/Tc = 0.5, ratio ~725) on 256 x 256 in the
+    default launch: observables after 100 and 200 steps, dv over the 100 steps between."""
+    wl = workload("droplet_4096_mrt", nx=256, ny=256, R=40.0)
+    say("[stats vs oracle] 256x256 MRT Guo+Li T/Tc 0.5")
+    rho0 = initial_density(wl)
+    p = oracle_params(wl)
+    probes = {"a": (128, 128), "b": (0, 0)}
+    lat = gpu_lattice(L, wl, L.LBM_PREC_MIXED)
+    lat.init(rho0)
+    lat.step(100)
+    s1 = lat.stats(track_dv=True)
+    f1 = lat.populations()
+    lat.step(100)
+    s2 = lat.stats(track_dv=True)
+    f2 = lat.populations()
+    assert s1["step"] == 100 and s2["step"] == 200 and s1["dv_max"] == 0.0 and s2["dv_max"] > 0
+    _check_same_state(s1, _oracle_observables(p, f1, probes), "step 100")
+    _check_same_state(s2, _oracle_observables(p, f2, probes, f_prev=f1), "step 200")
+    g1 = O.step(p, O.init_feq(rho0), 100)
+    g2 = O.step(p, g1, 100)
+    _check_trajectory(s2, _oracle_observables(p, g2, probes, f_prev=g1), "step 200")
+
+
+# Four kinds (forcing, collision) and uneven sizes, down to 3 x 5.
+MEMBERS = [
+    dict(nx=130, ny=70, T_over_Tc=0.8, K=1.0, scheme="EDM", A=-0.26, collision="BGK", tau=1.0),
+    dict(nx=96, ny=64, T_over_Tc=0.7, K=0.3, scheme="GUO", A=-0.5, collision="MRT", tau=0.9),
+    dict(nx=200, ny=77, T_over_Tc=0.6, K=1 / 49, scheme="GUO_LI", sigma=0.125, collision="BGK",
+         tau=0.6),
+    # a 3 x 5 box cannot hold two phases: its droplet dissolves, carried by a uniform velocity
+    # (inside the spinodal it would grow from rounding noise instead, which no FP32 state
+    # follows to 1e-5)
+    dict(nx=3, ny=5, T_over_Tc=0.9, K=1.0, scheme="GUO_LI", sigma=0.125, collision="MRT",
+         tau=0.7, u0=(0.02, -0.01)),
+    dict(nx=61, ny=45, T_over_Tc=0.5, K=1 / 49, scheme="GUO_LI", sigma=0.125, collision="MRT",
+         tau=1.0),
+]
+DROPPED = 2  # dropped after the first block of steps, re-activated after the second
+
+
+def _member_params(m):
+    wl = dict(m, A=m.get("A", 0.0), sigma=m.get("sigma", 0.0))
+    return oracle_params(wl)
+
+
+def _member_u0(m):
+    """Initial velocity field [ny][nx][2] of a member (None: rest)."""
+    if "u0" not in m:
+        return None
+    u = np.empty((m["ny"], m["nx"], 2))
+    u[..., 0], u[..., 1] = m["u0"]
+    return u
+
+
+def _member_rho0(m):
+    g, l, _ = TH.maxwell(m["T_over_Tc"])
+    return inputs.droplet(m["nx"], m["ny"], max(1.0, min(m["nx"], m["ny"]) / 4), 5.0, l, g)
+
+
+@pytest.mark.parametrize("flags", [16, 0])
+def test_batch_members_against_oracle(L, flags):
+    """Blocks of 42, 18 and 40 steps (42 and 18 are 2 mod 4: the two-step launches end with two
+    one-step launches); member 2 sits out the middle block, so it ends at 82 steps and the
+    others at 100.  Every member is compared with the oracle after its own step count, and the
+    batch's observables with the oracle's on the members' populations."""
+    say(f"[batch vs oracle] flags {flags}")
+    b = L.Batch(MEMBERS, tx=256, flags=flags)
+    rho0 = [_member_rho0(m) for m in MEMBERS]
+    for i, m in enumerate(MEMBERS):
+        b.init(i, rho0[i], _member_u0(m))
+    b.step(42)
+    b.set_active(DROPPED, 0)
+    b.step(18)
+    b.set_active(DROPPED, 1)
+    b.stats(track_dv=True)  # the velocity the next tracked call measures dv against
+    f_prev = [b.populations(i) for i in range(len(MEMBERS))]
+    b.step(40)
+    s = b.stats(track_dv=True)
+    for i, m in enumerate(MEMBERS):
+        steps = 82 if i == DROPPED else 100
+        assert b.steps(i) == steps and s[i]["step"] == steps
+        p = _member_params(m)
+        u0 = _member_u0(m)
+        f0 = O.init_feq(rho0[i]) if u0 is None else O.init_feq(rho0[i], u0[..., 0], u0[..., 1])
+        fl = O.fields(p, O.step(p, f0, steps))
+        rho, u = b.read(i)
+        e_rho, e_v = errors(rho, u, fl)
+        say(f"    member {i} {m['nx']}x{m['ny']} {m['scheme']}/{m['collision']} {steps} steps: "
+            f"rho {e_rho:.3e}  v {e_v:.3e}  (max |v| {np.abs(fl['vx']).max():.2e}, "
+            f"{np.abs(fl['vy']).max():.2e})")
+        assert e_rho < TOL and e_v < TOL, i
+        probes = {"a": (m["nx"] // 2, m["ny"] // 2), "b": (0, 0)}
+        _check_same_state(s[i], _oracle_observables(p, b.populations(i), probes,
+                                                    f_prev=f_prev[i]), f"member {i} stats")
