@@ -16,8 +16,10 @@ density ratio that the two are measured against.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
+import os
 import sys
 import time
 
@@ -27,6 +29,13 @@ from . import inputs, sweep
 
 DIMS = [4, 128, 128, 128, 64]
 K_RANGE = (1 / 49, 1 / 10)
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# The trained network (weights only: params, mean, std) and the record of its training draw.
+NET_PATH = os.path.join(_HERE, "warmstart_net.npz")
+NET_MANIFEST = os.path.join(_HERE, "warmstart_net.json")
+# Per-member step budgets of the 64-lattice sweep at equal density-ratio accuracy (written by
+# `--equal-accuracy --record`), with the converged ratios they were measured against.
+EQUAL_ACCURACY_PATH = os.path.join(_HERE, "warmstart_equal_accuracy.json")
 
 
 def say(*a):
@@ -126,6 +135,20 @@ class Surrogate:
         if not np.all(np.isfinite(prof)):
             return plain
         return sweep.WarmStart(prof, m["R"], plain.sum(), plain)
+
+
+def net_digest(path=NET_PATH):
+    """Short hash of a saved network file (ties results to the weights they came from)."""
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def load_surrogate(lbm, path=NET_PATH):
+    """The trained network from a weights-only file (no pickled objects)."""
+    d = np.load(path, allow_pickle=False)
+    sur = Surrogate(lbm, seed=0)
+    sur.net.set_params(d["params"])
+    sur.mean, sur.std = d["mean"].astype(np.float32), d["std"].astype(np.float32)
+    return sur
 
 
 def _start(lbm, sur, members, mode):
@@ -232,6 +255,7 @@ def equal_accuracy(lbm, sur, members, eps=1e-4, tol=2.5e-10, tol_rho=5e-10, chec
     ref = [(a + b) / 2 for a, b in zip(fin["tanh"], fin["learned"])]
     res["reference_spread_max"] = float(max(abs(a - b) / r for a, b, r in
                                             zip(fin["tanh"], fin["learned"], ref)))
+    res["reference_ratio"] = [float(r) for r in ref]
     for mode in ("tanh", "learned"):
         budgets = [time_to_accuracy(h, r, eps) for h, r in zip(hist[mode], ref)]
         wall, lu, ratios, fb = budgeted(lbm, members, _start(lbm, sur, members, mode), budgets,
@@ -311,6 +335,9 @@ def main(argv=None):
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--equal-accuracy", action="store_true",
                     help="time both starts to the same density-ratio accuracy (eps 1e-4)")
+    ap.add_argument("--record", default=None,
+                    help="with --equal-accuracy: write the per-member budgets and converged "
+                         "ratios (the benchmark's warm-start leg replays them)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from . import lbm
@@ -318,10 +345,8 @@ def main(argv=None):
     out = {"dims": DIMS}
     sur = Surrogate(lbm, seed=0)
     if a.load_net:
-        d = np.load(a.load_net)
-        sur.net.set_params(d["params"])
-        sur.mean, sur.std = d["mean"], d["std"]
-        out["training"] = {"loaded": a.load_net}
+        sur = load_surrogate(lbm, a.load_net)
+        out["training"] = {"loaded": a.load_net, "net_sha256_16": net_digest(a.load_net)}
     else:
         sets, out["generation"] = [], []
         if a.data:
@@ -355,6 +380,20 @@ def main(argv=None):
                                                        n_levels=a.eval_levels))
         out["equal_accuracy"] = equal_accuracy(lbm, sur, ev)
         e = out["equal_accuracy"]
+        if a.record:
+            rec = {"eps": e["eps"], "seed": a.eval_seed, "count": a.eval_count,
+                   "levels": a.eval_levels, "check_every": 500,
+                   "net_sha256_16": net_digest(a.load_net) if a.load_net else None,
+                   "reference_ratio": e["reference_ratio"],
+                   "reference_spread_max": e["reference_spread_max"],
+                   "budgets": {m: e[m]["steps"] for m in ("tanh", "learned")},
+                   "measured": {m: {k: e[m][k] for k in ("wall_s", "lattice_updates",
+                                                         "ratio_err_max")}
+                                for m in ("tanh", "learned")},
+                   "members": [{k: m[k] for k in ("nx", "T_over_Tc", "tau", "collision")}
+                               for m in ev]}
+            with open(a.record, "w") as fh:
+                json.dump(rec, fh, indent=1)
         say(json.dumps({k: e[k] for k in ("eps", "reference_spread_max", "speedup_wall",
                                           "speedup_updates")}
                        | {m: {k: e[m][k] for k in ("wall_s", "lattice_updates", "ratio_err_max",

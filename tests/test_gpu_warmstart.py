@@ -1,8 +1,10 @@
 """Warm-start initial states on the device (lbm_batch_init_rest, lbm_batch_init_profile)
 against the oracle of the rest state, the profile expansion and the mass matching; error
-paths; and the gain itself: a lattice started at rest from its own equilibrium density needs
+paths; the bound on the gain (a lattice started at rest from its own equilibrium density needs
 far fewer steps than the tanh start and reaches the same density ratio, and so, to a lesser
-degree, does the mass-matched radial profile of that equilibrium."""
+degree, does the mass-matched radial profile of that equilibrium); and the gain of the trained
+network itself on lattices of the batched sweep's distribution, against the tanh start and
+against a constant profile."""
 import oracle
 from oracle import thermo as TH
 import numpy as np
@@ -105,10 +107,11 @@ def test_rest_state_matches_oracle(L):
     assert np.max(np.abs(v)) < 1e-6
 
 
-def test_warm_start_gain(L):
-    """From the droplet's own equilibrium density at physical rest: at most half the steps of
-    the tanh start, same density ratio.  From the mass-matched radial profile of that
-    equilibrium (64 samples along +x, centred on the interface): fewer steps, same ratio."""
+def test_equilibrium_profile_start_gain(L):
+    """The bound on any learned start.  From the droplet's own equilibrium density at physical
+    rest: at most half the steps of the tanh start, same density ratio.  From the mass-matched
+    radial profile of that equilibrium (64 samples along +x, centred on the interface): fewer
+    steps, same ratio."""
     from paper_1412_5170_amd import sweep
     m = dict(sweep.PHYSICS, nx=128, ny=128, T_over_Tc=0.7, tau=1.0, collision="BGK", R=32.0)
     plain = sweep.tanh_density(L, m)
@@ -132,3 +135,41 @@ def test_warm_start_gain(L):
     assert s2[0] < s0[0]
     assert abs(ratio1 - ratio0) / ratio0 < 1e-4
     assert abs(ratio2 - ratio0) / ratio0 < 1e-4
+
+
+def test_trained_network_gain(L):
+    """The committed network (weights-only file) as the initial state of eight lattices drawn
+    like the batched sweep (sizes 128^2-320^2, R = n/4, tau in [0.6, 1.5], T/Tc in [0.5, 0.9],
+    BGK or MRT, Guo + Li, K = 1/49), against the plain tanh start and against a constant
+    profile (the network's mean output, the same for every lattice, mass-matched the same way).
+    Each start runs under a stopping rule 4x tighter than the sweep's, recording the probe
+    density ratio every 500 steps; the converged ratio of a lattice is the mean of the tanh and
+    learned end points, and a start's cost is the lattice updates until its ratio stays within
+    1e-4 of it.  The network must reach that band with at most 0.85x the tanh start's updates,
+    and the constant profile must not do as well as the network."""
+    from paper_1412_5170_amd import sweep, warmstart as WS
+    members = sweep.members_from_draw(inputs.batch_draw(5, count=8, n_levels=13))
+    sur = WS.load_surrogate(L)
+    rule = dict(tol=2.5e-10, tol_rho=5e-10, check_every=500, max_steps=1_500_000)
+    starts = {"tanh": WS._start(L, sur, members, "tanh"),
+              "learned": WS._start(L, sur, members, "learned")}
+    assert all(isinstance(w, sweep.WarmStart) for w in starts["learned"])
+    const = []
+    for m, w in zip(members, starts["learned"]):
+        const.append(sweep.WarmStart(sur.mean.astype(np.float64), m["R"], w.mass, w.fallback))
+    starts["constant"] = const
+    hist, fin = {}, {}
+    for mode, inits in starts.items():
+        hist[mode], fin[mode] = WS.trajectories(L, members, inits, label=mode, **rule)
+    ref = [(a + b) / 2 for a, b in zip(fin["tanh"], fin["learned"])]
+    spread = max(abs(a - b) / r for a, b, r in zip(fin["tanh"], fin["learned"], ref))
+    cost = {}
+    for mode in starts:
+        steps = [WS.time_to_accuracy(h, r, 1e-4) for h, r in zip(hist[mode], ref)]
+        cost[mode] = sum(m["nx"] * m["ny"] * st for m, st in zip(members, steps))
+        say(f"trained network gain: {mode} steps {steps}, {cost[mode] / 1e9:.2f} G updates")
+    say(f"    learned / tanh {cost['learned'] / cost['tanh']:.3f}, constant / tanh "
+        f"{cost['constant'] / cost['tanh']:.3f}; end-point spread {spread:.1e}")
+    assert spread < 1e-4
+    assert cost["learned"] <= 0.85 * cost["tanh"]
+    assert cost["constant"] > cost["learned"]
