@@ -1,23 +1,31 @@
-"""Benchmark of the pseudo-potential D2Q9 LBM time step on one MI355X.
+"""Benchmark of the pseudo-potential D2Q9 LBM on one MI355X.
 
-Workload (default): the 4096 x 4096 periodic static droplet, radius 600, tanh interface of
-width 5 from the Maxwell coexistence densities at T/Tc = 0.5 (ratio ~725), MRT collision
-(s_rho = s_j = 1, s_e = s_eps = s_q = 1.1, s_nu = 1/tau, tau = 1), Guo forcing with Li's
-modified force term (sigma = 0.125), Carnahan-Starling EOS rescaled by K = 1/49.
-A step is one full time step (psi from the populations, force, forcing, collision, streaming)
-and the FP64 observables reduction runs every --stats-every steps inside the timed region, as a
-production run would.  Inputs are resident in HBM before timing starts.  By default the library's
-default launch runs: the two-step sweep (two time steps per pass over HBM, 64-lane strips of 58
-output columns over 16-row segments); --kernel sweep runs the one-step sweep (512-column strips,
-8-row segments, two rows of loads in flight, XCD-ordered tiles), --kernel two_pass the
-density/psi pass and the fused pass; --autotune lets the library's autotuner pick (timed
-trials on the initial state, which it restores, before the warm-up), --launch sets the shape.
+Main leg (the JSON line's `value`): MLUPS of the 4096 x 4096 periodic static droplet, radius
+600, tanh interface of width 5 from the Maxwell coexistence densities at T/Tc = 0.5 (ratio
+~725), MRT collision (s_rho = s_j = 1, s_e = s_eps = s_q = 1.1, s_nu = 1/tau, tau = 1), Guo
+forcing with Li's modified force term (sigma = 0.125), Carnahan-Starling EOS rescaled by
+K = 1/49.  A step is one full time step (psi from the populations, force, forcing, collision,
+streaming); the FP64 observables reduction runs every --stats-every steps inside the timed
+region, as a production run would.  Inputs are resident in HBM before timing starts.  Before
+the W warm-up steps the lattice steps for --settle-seconds of wall time, so that the timed
+steps do not run on a GPU still raising its clocks.  By default the library's default launch
+runs (the two-step sweep); --kernel sweep / two_pass select the one-step sweep or the
+two-pass step, --autotune lets the library's autotuner pick, --launch sets the shape.
 
-Prints ONE JSON line: MLUPS, the roofline of the dominant kernel measured with HIP events on the
-lattice's stream (the two-step sweep against the vector ALU peak -- algorithmic flops per launch
-/ average launch time -- with its HBM figures and its VALU issue rate alongside; the one-step
-kernels against HBM), the same for the alternative kernel, and the FP64 oracle's MLUPS on the
-host cores (cpu_baseline).
+`roofline` is the dominant kernel's HBM rate: algorithmic bytes per launch (72 B per node and
+time step: nine FP32 populations read and nine written, two time steps per launch of the
+two-step sweep) over the kernel's average launch time from HIP events on the lattice's stream,
+against 8 TB/s; the real traffic (rocprofv3 counters of the same source), the VALU issue rate
+and the vector-ALU flop rate stand beside it.
+
+Further legs (each can be switched off): the same for the alternative kernel; `batch`, the
+64-lattice droplet draw of the batched sweep (sizes 128^2-1024^2) stepped a fixed number of
+steps (GLUPS); `sweep`, that draw run to equilibrium from tanh starts (max |v| change per step
+< 1e-9 and probe densities changing < 2e-9 per step, checked every 500 steps): wall time and
+steps; `warm_start`, the same draw started from the learned network's profiles vs tanh, each
+lattice stepped exactly as far as the recorded equal-accuracy budgets say (density ratio within
+1e-4 of the converged one), wall time of both and the ratio errors reached; and `cpu_baseline`,
+the FP64 oracle on the host cores (one thread and all threads).
 
 --copy-probe instead times the library's plain copy kernel on a buffer the size of one
 population buffer (the scale reference for the HBM counters).
@@ -55,7 +63,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="droplet_4096_mrt")
-    ap.add_argument("--precision", default="mixed", choices=["f32", "f64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["f64", "mixed"])
     ap.add_argument("--kernel", default="sweep2", choices=["sweep2", "sweep", "two_pass"],
                     help="sweep2: two steps per launch (the library's default); sweep: one step")
     ap.add_argument("--autotune", action="store_true",
@@ -67,8 +75,13 @@ def parse():
                     help="steps of the two-pass variant timed beside the main result (0: skip)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-every", type=int, default=100)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="approximate CPU time budget of the oracle baseline sample")
+    ap.add_argument("--settle-seconds", type=float, default=2.0,
+                    help="wall seconds of stepping before the warm-up steps (GPU clocks)")
+    ap.add_argument("--batch-steps", type=int, default=2000,
+                    help="steps of the 64-lattice batch leg (0: skip)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the time-to-equilibrium legs (sweep and warm start)")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel HIP events (for profiler runs)")
@@ -81,46 +94,72 @@ def kernel_source_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def cpu_baseline(wl, budget_s):
-    """The FP64 oracle on a bounded sample of the same physics: a 512 x 512 cut of the
-    workload (droplet radius scaled with the side), as many steps as fit the budget."""
+def _oracle_run(O, p, f, steps):
+    """Wall seconds of `steps` oracle steps (after one untimed step: thread start, first
+    touch)."""
+    f = O.step(p, f, 1)
+    t0 = time.perf_counter()
+    O.step(p, f, steps)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle (plain C, OpenMP over rows) on bounded samples of the benchmark's
+    workloads, on all of the host's threads and on one: the 4096^2 MRT droplet itself for 20
+    steps (all threads; `value`), a 256^2 cut of its physics on one thread, and the 512^2 BGK
+    Guo + Li droplet at T/Tc = 0.6, K = 1/49 (radius 80) for 200 steps on all threads and 20 on
+    one.  MLUPS = nodes x steps / wall seconds; the oracle moves 144 B per lattice update in
+    FP64."""
     import oracle as O
     from oracle import thermo as TH
     from paper_1412_5170_amd import inputs
 
-    if wl["init"] == "droplet" and wl["nx"] > 512:
-        sample = dict(wl, nx=512, ny=512, R=wl["R"] * 512 / wl["nx"])
-    else:
-        sample = dict(wl)
-    g, l, _ = TH.maxwell(wl["T_over_Tc"])
-    rho0 = inputs.initial_density(sample, l, g)
-    tau = wl["tau"]
-    s = wl.get("s", (1.0, 1.1, 1.1, 1.0, 1.1))
-    s = (s[0], s[1], s[2], s[3], s[4], s[3], s[4], 1 / tau, 1 / tau)
-    p = O.Params(nx=sample["nx"], ny=sample["ny"], T=TH.temperature(wl["T_over_Tc"]), tau=tau,
-                 scheme=getattr(O, wl["scheme"]), collision=getattr(O, wl["collision"]),
-                 K=wl["K"], A=wl["A"], sigma=wl["sigma"], s=s)
-    f = O.init_feq(rho0)
-    f = O.step(p, f, 1)                      # warm-up (thread start, first touch)
-    # chunks of growing length until the budget is spent: no estimate from a first step
-    steps, chunk = 0, 4
-    t0 = time.perf_counter()
-    while True:
-        f = O.step(p, f, chunk)
-        steps += chunk
-        dt = time.perf_counter() - t0
-        if dt >= budget_s:
-            break
-        chunk = min(2 * chunk, 256)
-    nodes = sample["nx"] * sample["ny"]
-    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"{sample['nx']}x{sample['ny']} lattice of the workload's physics (droplet "
-                      f"radius scaled with the side), {steps} FP64 steps, {dt:.1f} s"}
+    def params(w):
+        tau = w["tau"]
+        s = w.get("s", (1.0, 1.1, 1.1, 1.0, 1.1))
+        s = (s[0], s[1], s[2], s[3], s[4], s[3], s[4], 1 / tau, 1 / tau)
+        return O.Params(nx=w["nx"], ny=w["ny"], T=TH.temperature(w["T_over_Tc"]), tau=tau,
+                        scheme=getattr(O, w["scheme"]), collision=getattr(O, w["collision"]),
+                        K=w["K"], A=w["A"], sigma=w["sigma"], s=s)
+
+    def state(w):
+        g, l, _ = TH.maxwell(w["T_over_Tc"])
+        return O.init_feq(inputs.initial_density(w, l, g))
+
+    all_threads = O.threads()
+    c2 = dict(inputs.WORKLOADS["droplet_512_li"])
+    cut = dict(wl, nx=256, ny=256, R=wl["R"] * 256 / wl["nx"])
+    runs = []
+    for name, w, steps, threads in ((f"{wl['nx']}x{wl['ny']} (the main leg's workload)", wl, 20,
+                                     all_threads),
+                                    ("256x256 cut of the main leg's physics", cut, 60, 1),
+                                    ("512x512 Guo + Li BGK droplet", c2, 200, all_threads),
+                                    ("512x512 Guo + Li BGK droplet", c2, 20, 1)):
+        O.set_threads(threads)
+        dt = _oracle_run(O, params(w), state(w), steps)
+        runs.append({"lattice": name, "threads": threads, "steps": steps,
+                     "seconds": round(dt, 2),
+                     "MLUPS": round(w["nx"] * w["ny"] * steps / dt / 1e6, 3)})
+    O.set_threads(all_threads)
+    main = runs[0]
+    return {"value": main["MLUPS"], "unit": "MLUPS", "cores": all_threads, "kind": "oracle",
+            "sample": f"{main['lattice']}, {main['steps']} FP64 steps in {main['seconds']} s on "
+                      f"{all_threads} threads",
+            "cpu": cpu_model(), "nproc": os.cpu_count(), "runs": runs}
 
 
-PRECISIONS = {"f32": 0, "f64": 1, "mixed": 2}
-DTYPE = {"f32": "f32", "f64": "f64 (f32 storage)", "mixed": "f32+f64 mixed (f32 storage)"}
+PRECISIONS = {"f64": 1, "mixed": 2}
+DTYPE = {"f64": "f64 (f32 storage)", "mixed": "f32+f64 mixed (f32 storage)"}
 
 
 def make_lattice(lbm, wl, args, kernel):
@@ -192,6 +231,140 @@ def copy_probe(args):
                                      "GBps": round(8 * n / dt / 1e9, 1)}}), flush=True)
 
 
+def settle(lat, seconds, torch):
+    """Step for `seconds` of wall time (chunks of 100 steps) before the warm-up, so that the
+    timed steps run at the clocks a long job runs at.  Returns the steps taken."""
+    if seconds <= 0:
+        return 0
+    torch.cuda.synchronize()
+    t0, n = time.perf_counter(), 0
+    while time.perf_counter() - t0 < seconds:
+        lat.step(100)
+        torch.cuda.synchronize()
+        n += 100
+    return n
+
+
+def roofline(kernel, ev, launch, nodes, args):
+    """HBM roofline of one launch of `kernel`: algorithmic bytes per launch over the average
+    launch time (HIP events around the timed region's launches), against 8 TB/s; the real
+    traffic, VALU issue and vector-ALU flop rates beside it."""
+    psi_ms, main_ms, nt = ev
+    steps_per_launch = 2 if kernel == "sweep2" else 1  # the two-step sweep: 2 per launch
+    avg = main_ms / 1e3 / (nt / steps_per_launch)     # per launch of the main kernel
+    per_node = FUSED_BYTES_PER_NODE if kernel == "two_pass" else SWEEP_BYTES_PER_NODE
+    algo_bytes = per_node * steps_per_launch * nodes  # per launch
+    achieved = algo_bytes / avg / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+         "kernel": {"sweep": "sweep_kernel", "sweep2": "sweep2_kernel",
+                    "two_pass": "fused_kernel"}[kernel],
+         "bytes_per_node_step": per_node, "steps_per_launch": steps_per_launch,
+         "algorithmic_bytes_per_launch": algo_bytes, "launches": int(nt // steps_per_launch),
+         "avg_us": round(avg * 1e6, 2)}
+    tflops = FLOPS_PER_NODE_STEP * steps_per_launch * nodes / avg / 1e12
+    r["alu"] = {"achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+                "flops_per_node_step": FLOPS_PER_NODE_STEP}
+    if kernel == "two_pass":
+        pavg = psi_ms / 1e3 / nt
+        r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),
+                         "achieved": round(PSI_BYTES_PER_NODE * nodes / pavg / 1e9, 1)}
+    if os.path.exists(PROFILE_TRAFFIC):
+        t = json.load(open(PROFILE_TRAFFIC))
+        key = f"{args.workload}/{kernel}/{args.precision}/{args.layout}"
+        # Counters are only valid for the kernel source and launch they were taken on.
+        if (key in t and t[key]["kernel_sha256_16"] == kernel_source_hash()
+                and list(t[key].get("launch", [])) == list(launch)):
+            r["traffic"] = t[key]["bytes_per_launch"]
+            r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] / algo_bytes, 4)
+            if "valu_insts_per_launch" in t[key]:  # wave instructions (SQ_INSTS_VALU)
+                lane_ops = 64 * t[key]["valu_insts_per_launch"] / avg
+                r["valu_issue"] = {"achieved": round(lane_ops / 1e12, 2),
+                                   "peak": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                                   "unit": "T lane-instructions/s",
+                                   "frac": round(lane_ops / VALU_LANE_OPS_PEAK, 4)}
+    return r
+
+
+def say(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def batch_leg(lbm, steps):
+    """The 64-lattice droplet draw of the batched sweep (seed 0: sizes 128^2-1024^2, R = n/4,
+    tau in [0.6, 1.5], T/Tc in [0.5, 0.9], BGK or MRT; Guo + Li, K = 1/49) from its tanh
+    starts, stepped `steps` steps with every lattice active (after one untimed block that also
+    captures the graph)."""
+    from paper_1412_5170_amd import inputs, sweep
+    members = sweep.members_from_draw(inputs.batch_draw(0))
+    b = lbm.Batch(members)
+    for i, m in enumerate(members):
+        b.init_rest(i, sweep.tanh_density(lbm, m))
+    b.step(steps)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    dt = time.perf_counter() - t0
+    nodes = sum(m["nx"] * m["ny"] for m in members)
+    del b
+    return {"lattices": len(members), "nodes": nodes, "steps": steps,
+            "seconds": round(dt, 4), "us_per_step": round(dt / steps * 1e6, 2),
+            "GLUPS": round(nodes * steps / dt / 1e9, 2),
+            "hbm_algorithmic": {"achieved": round(72 * nodes * steps / dt / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(72 * nodes * steps / dt / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
+def sweep_leg(lbm):
+    """Time to equilibrium of the 64-lattice draw from tanh starts (the batched sweep's own
+    stopping rule)."""
+    from paper_1412_5170_amd import inputs, sweep
+    members = sweep.members_from_draw(inputs.batch_draw(0))
+    inits = [sweep.tanh_density(lbm, m) for m in members]
+    wall, steps, status, b = sweep.run_batch(lbm, members, inits, tol=1e-9, tol_rho=2e-9,
+                                             check_every=500, max_steps=1_000_000,
+                                             chunk=100_000, report=say)
+    del b
+    lu = sum(m["nx"] * m["ny"] * st for m, st in zip(members, steps))
+    return {"wall_s": round(wall, 2), "lattice_updates": int(lu),
+            "GLUPS": round(lu / wall / 1e9, 2), "converged": int(sum(s == 0 for s in status)),
+            "lattices": len(members), "max_steps": int(max(steps)),
+            "rule": "max |v(t) - v(t-500)| / 500 < 1e-9 and probe densities changing < 2e-9 "
+                    "per step, checked every 500 steps"}
+
+
+def warm_start_leg(lbm):
+    """The learned warm start against tanh starts on the 64-lattice draw at equal accuracy:
+    each lattice steps exactly its recorded budget (the first step from which its density
+    ratio stays within 1e-4 of the converged ratio, from trajectories under a 4x tighter rule),
+    and the ratios reached are measured against the recorded converged ratios."""
+    from paper_1412_5170_amd import inputs, sweep, warmstart as WS
+    if not os.path.exists(WS.EQUAL_ACCURACY_PATH):
+        return {"skipped": "no equal-accuracy record"}
+    rec = json.load(open(WS.EQUAL_ACCURACY_PATH))
+    if rec.get("net_sha256_16") != WS.net_digest():
+        return {"skipped": "the equal-accuracy record belongs to another network"}
+    members = sweep.members_from_draw(inputs.batch_draw(rec["seed"], count=rec["count"],
+                                                        n_levels=rec["levels"]))
+    sur = WS.load_surrogate(lbm)
+    ref = rec["reference_ratio"]
+    out = {"eps": rec["eps"], "lattices": len(members), "net_sha256_16": rec["net_sha256_16"]}
+    for mode in ("tanh", "learned"):
+        inits = WS._start(lbm, sur, members, mode)
+        wall, lu, ratios, fb = WS.budgeted(lbm, members, inits, rec["budgets"][mode],
+                                           rec["check_every"], mode)
+        err = [abs(x - r) / r for x, r in zip(ratios, ref)]
+        out[mode] = {"wall_s": round(wall, 2), "lattice_updates": int(lu),
+                     "ratio_err_max": float(max(err)), "fallbacks": fb}
+        say(f"warm start {mode}: {wall:.1f} s, ratio error max {max(err):.2e}")
+    out["speedup_wall"] = round(out["tanh"]["wall_s"] / out["learned"]["wall_s"], 3)
+    out["speedup_updates"] = round(out["tanh"]["lattice_updates"] /
+                                   out["learned"]["lattice_updates"], 3)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -220,56 +393,18 @@ def main():
         # the warm-up and outside the timed region
         tuned_ms = lat.autotune(None, trial_steps=50)
     launch = lat.get_launch()
-    print(f"bench: {args.workload} {wl['nx']}x{wl['ny']} {args.precision} {args.kernel} "
-          f"launch {launch}, warmup {args.warmup}", file=sys.stderr, flush=True)
+    say(f"{args.workload} {wl['nx']}x{wl['ny']} {args.precision} {args.kernel} launch {launch}, "
+        f"settle {args.settle_seconds} s, warmup {args.warmup}")
+    settled = settle(lat, args.settle_seconds, torch)
+    lat.init(rho0)  # the timed steps start from the workload's initial state again
     lat.step(args.warmup)
     st0 = lat.stats()
     elapsed, ev = timed(lat, args.steps, args.stats_every, torch, timing)
     st = lat.stats()
-    print(f"bench: {args.steps} steps in {elapsed:.3f} s; mass drift "
-          f"{(st['mass'] - st0['mass']) / st0['mass']:.2e}; us_max {st['us_max']:.3e}; "
-          f"ratio {st['ratio']:.2f}", file=sys.stderr, flush=True)
+    say(f"{args.steps} steps in {elapsed:.4f} s; mass drift "
+        f"{(st['mass'] - st0['mass']) / st0['mass']:.2e}; us_max {st['us_max']:.3e}; "
+        f"ratio {st['ratio']:.2f}")
     del lat
-
-    def roofline(kernel, ev, launch):
-        psi_ms, main_ms, nt = ev
-        steps_per_launch = 2 if kernel == "sweep2" else 1  # the two-step sweep: 2 per launch
-        avg = main_ms / 1e3 / (nt / steps_per_launch)     # per launch of the main kernel
-        per_node = FUSED_BYTES_PER_NODE if kernel == "two_pass" else SWEEP_BYTES_PER_NODE
-        achieved = per_node * nodes / avg / 1e9
-        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-             "kernel": {"sweep": "sweep_kernel", "sweep2": "sweep2_kernel",
-                        "two_pass": "fused_kernel"}[kernel],
-             "bytes_per_node": per_node, "steps_per_launch": steps_per_launch,
-             "avg_us": round(avg * 1e6, 2)}
-        if kernel == "sweep2":
-            # Two steps per pass over HBM: the kernel is bound by vector ALU issue, not HBM.
-            tflops = FLOPS_PER_NODE_STEP * steps_per_launch * nodes / avg / 1e12
-            hbm = {k: r[k] for k in ("achieved", "peak", "unit", "frac", "bytes_per_node")}
-            r.update(bound="alu", achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS,
-                     unit="TFLOP/s", frac=round(tflops / ALU_PEAK_TFLOPS, 4),
-                     flops_per_node_step=FLOPS_PER_NODE_STEP, hbm=hbm)
-        if kernel == "two_pass":
-            pavg = psi_ms / 1e3 / nt
-            r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),
-                             "achieved": round(PSI_BYTES_PER_NODE * nodes / pavg / 1e9, 1)}
-        if os.path.exists(PROFILE_TRAFFIC):
-            t = json.load(open(PROFILE_TRAFFIC))
-            key = f"{args.workload}/{kernel}/{args.precision}/{args.layout}"
-            # Counters are only valid for the kernel source and launch they were taken on.
-            if (key in t and t[key]["kernel_sha256_16"] == kernel_source_hash()
-                    and list(t[key].get("launch", [])) == list(launch)):
-                r["traffic"] = t[key]["bytes_per_launch"]
-                r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] /
-                                                      (per_node * nodes), 4)
-                if "valu_insts_per_launch" in t[key]:  # wave instructions (SQ_INSTS_VALU)
-                    lane_ops = 64 * t[key]["valu_insts_per_launch"] / avg
-                    r["valu_issue"] = {"achieved": round(lane_ops / 1e12, 2),
-                                       "peak": round(VALU_LANE_OPS_PEAK / 1e12, 2),
-                                       "unit": "T lane-instructions/s",
-                                       "frac": round(lane_ops / VALU_LANE_OPS_PEAK, 4)}
-        return r
 
     mlups = nodes * args.steps / elapsed / 1e6
     out = {
@@ -283,15 +418,15 @@ def main():
                    "T_over_Tc": wl["T_over_Tc"], "K": wl["K"], "tau": wl["tau"],
                    "kernel": args.kernel, "launch": list(launch),
                    "autotuned": tuned_ms is not None, "layout": args.layout,
-                   "stats_every": args.stats_every, "parallelism": "single GPU"},
-        "roofline": roofline(args.kernel, ev, launch) if ev else None,
+                   "stats_every": args.stats_every, "settle_seconds": args.settle_seconds,
+                   "settle_steps": settled, "parallelism": "single GPU"},
+        "roofline": roofline(args.kernel, ev, launch, nodes, args) if ev else None,
     }
     if out["roofline"] is not None:
-        # The whole job's rate at the method's minimum of 72 B per lattice update (one read
-        # and one write of the nine FP32 populations): the HBM rate a one-step kernel would
-        # need for the same throughput.
+        # The whole job's rate at the method's minimum of 72 B per lattice update, observables
+        # and launch gaps included.
         gbs = mlups * SWEEP_BYTES_PER_NODE / 1e3
-        out["roofline"]["algorithmic_fraction"] = {
+        out["roofline"]["whole_job"] = {
             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "basis": "whole-job MLUPS x 72 B per lattice update"}
@@ -304,11 +439,20 @@ def main():
         el2, ev2 = timed(lat, args.alt_steps, args.stats_every, torch, True)
         del lat
         out["alternative"] = {"kernel": alt, "MLUPS": round(nodes * args.alt_steps / el2 / 1e6, 1),
-                              "roofline": roofline(alt, ev2, alt_launch)}
+                              "roofline": roofline(alt, ev2, alt_launch, nodes, args)}
     del rho0
     torch.cuda.empty_cache()
+    if args.batch_steps:
+        out["batch"] = batch_leg(lbm, args.batch_steps)
+        say(f"batch: {out['batch']['GLUPS']} GLUPS, {out['batch']['us_per_step']} us per step")
+    if not args.no_sweep:
+        out["sweep"] = sweep_leg(lbm)
+        say(f"sweep to equilibrium: {out['sweep']['wall_s']} s")
+        if not args.no_warm_start:
+            out["warm_start"] = warm_start_leg(lbm)
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 
 

@@ -76,12 +76,18 @@ def lib():
         _lib.orc_mrt_matrix.argtypes = [dp, dp]
         _lib.orc_guo_bracket.argtypes = [ctypes.c_double] * 4 + [dp]
         _lib.orc_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
     return _lib
 
 
 def threads() -> int:
     """OpenMP threads the stepper runs on."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the stepper's later parallel loops on n threads."""
+    lib().orc_set_threads(int(n))
 
 
 class OracleError(RuntimeError):

@@ -462,6 +462,9 @@ void orc_guo_bracket(double Fx, double Fy, double Vx, double Vy, double *out)
 #ifdef _OPENMP
 #include <omp.h>
 int orc_threads(void) { return omp_get_max_threads(); }
+/* Threads of the later parallel loops (for timing the stepper on one core). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int orc_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif
