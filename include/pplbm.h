@@ -232,6 +232,21 @@ int lbm_load(lbm_t *h, const char *path);
  * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. Synchronises. */
 int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out);
 
+/* Allocation-free variant of lbm_stats, for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_stats with track_dv = 0 and without the
+ * reduction buffers lbm_stats allocates on first use.  It runs the same kernels on the same
+ * block partition, so it reports the same values bit for bit (dv_max = 0: no velocity history).
+ * The reduction's partial results and result vector live in a fixed device array of the
+ * library, 2048 x 6 + 8 doubles (96.06 KiB) on each GPU it runs on, held until the process
+ * ends; every lattice fits (the reduction uses at most 2048 blocks), and a larger need would
+ * return LBM_EINVAL.  All calls on one GPU share that array; each call writes everything it
+ * reads, so nothing needs clearing, but calls that overlap on one GPU (two threads, two
+ * streams) race on it and must be serialised by the caller.  The handle's GPU must be the
+ * current device; needs lbm_init or lbm_set_populations first (LBM_ESTATE).  Calls no
+ * allocator; synchronises the handle's stream (so it cannot be recorded into a graph).
+ * Returns LBM_EUNSTABLE (with *out filled) when a node is non-finite. */
+int lbm_stats_noalloc(lbm_t *h, lbm_stats_t *out);
+
 /* Autotuner: times trial_steps steps (rounded up to even) of the one-pass sweep for strip widths
  * tx in {64, 128, 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets
  * XCD|SHALLOW, SHALLOW, XCD, XCD|SHALLOW|NONTEMPORAL, and of the two-step sweep for tx in

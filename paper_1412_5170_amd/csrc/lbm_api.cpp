@@ -866,6 +866,24 @@ int lbm_set_populations(lbm_t *h, const float *f) {
     return LBM_OK;
 }
 
+// lbm_stats_t from the reduction's result vector (sum, min, max, max |v|, max |dv|,
+// non-finite count, probe a, probe b); dv_max only when a previous velocity was kept.
+static int fill_stats(lbm *h, const double r[pplbm::kStatsOut], bool dv, lbm_stats_t *out) {
+    out->mass = r[0];
+    out->rho_min = r[1];
+    out->rho_max = r[2];
+    out->us_max = r[3];
+    out->dv_max = dv ? r[4] : 0.0;
+    out->nonfinite = (int)r[5];
+    out->rho_probe_a = r[6];
+    out->rho_probe_b = r[7];
+    const double hi = std::fmax(r[6], r[7]), lo = std::fmin(r[6], r[7]);
+    out->ratio = hi / lo;
+    out->step = h->step;
+    if (out->nonfinite) return fail(h, LBM_EUNSTABLE, "non-finite or undefined state at some node");
+    return LBM_OK;
+}
+
 int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out) {
     if (!h || !out) return LBM_EINVAL;
     if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_stats before lbm_init");
@@ -886,20 +904,29 @@ int lbm_stats(lbm_t *h, int track_dv, lbm_stats_t *out) {
     double r[pplbm::kStatsOut];
     HIP_TRY(h, hipMemcpyAsync(r, h->stats_out, sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    out->mass = r[0];
-    out->rho_min = r[1];
-    out->rho_max = r[2];
-    out->us_max = r[3];
-    out->dv_max = (track_dv && h->vprev_valid) ? r[4] : 0.0;
-    out->nonfinite = (int)r[5];
-    out->rho_probe_a = r[6];
-    out->rho_probe_b = r[7];
-    const double hi = std::fmax(r[6], r[7]), lo = std::fmin(r[6], r[7]);
-    out->ratio = hi / lo;
-    out->step = h->step;
+    const bool dv = track_dv && h->vprev_valid;
     if (track_dv) h->vprev_valid = true;
-    if (out->nonfinite) return fail(h, LBM_EUNSTABLE, "non-finite or undefined state at some node");
-    return LBM_OK;
+    return fill_stats(h, r, dv, out);
+}
+
+int lbm_stats_noalloc(lbm_t *h, lbm_stats_t *out) {
+    if (!h || !out) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "lbm_stats_noalloc before lbm_init");
+    double *scr = nullptr;
+    size_t cap = 0;
+    HIP_TRY(h, pplbm::stats_scratch(&scr, &cap));
+    const size_t parts = pplbm::stats_partial_count(h->p) * pplbm::kStatsFields;
+    if (parts + pplbm::kStatsOut > cap)
+        return fail(h, LBM_EINVAL, "lbm_stats_noalloc: the reduction needs more partials than "
+                                   "the library's fixed device array holds");
+    float *fc = h->f[h->cur];
+    HIP_TRY(h, pplbm::launch_psi(h->p, pplbm::kPrecF64, 0, fc, h->psi, h->stream));
+    HIP_TRY(h, pplbm::launch_stats(h->p, fc, h->psi, nullptr, scr, scr + parts, h->xa, h->ya,
+                                   h->xb, h->yb, h->stream));
+    double r[pplbm::kStatsOut];
+    HIP_TRY(h, hipMemcpyAsync(r, scr + parts, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return fill_stats(h, r, false, out);
 }
 
 int lbm_timing_enable(lbm_t *h, int enable) {

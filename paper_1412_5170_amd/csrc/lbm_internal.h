@@ -97,6 +97,10 @@ hipError_t launch_stats(const Physics &p, const float *f, const float *psi, floa
                         double *partial, double *out, int xa, int ya, int xb, int yb,
                         hipStream_t stream);
 
+// The library's fixed device array for the allocation-free observables on the current device:
+// *ptr receives its device address (looked up once per device), *doubles its length.
+hipError_t stats_scratch(double **ptr, size_t *doubles);
+
 hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t stream);
 
 // ---- batched sweep ----------------------------------------------------------------------

@@ -27,6 +27,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "lbm_internal.h"
 
@@ -1558,6 +1559,41 @@ hipError_t launch_batch_stats(const void *lats, const int4 *sblocks, int nsblock
     hipLaunchKernelGGL(batch_stats_final_kernel, dim3(nlat), dim3(kStatsBlock), 0, s, L, ranges, ids,
                        parity, partial, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free observables (lbm_stats_noalloc): the reduction's block partials and its
+// result vector live in one fixed device array, one copy per GPU, held until the process ends.
+// Every reduction writes all the partials and results it reads, so nothing is cleared between
+// calls; calls that overlap on one GPU race on it.  Host code never passes the array's name to
+// a kernel or a copy (in host code it is a stand-in, not a device address): it takes the
+// address hipGetSymbolAddress reports for the current device, looked up once per device.
+// ---------------------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = (size_t)kStatsMaxBlocks * kStatsFields + kStatsOut;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex scratch_mutex;
+double *scratch_dev[kScratchMaxDevices];  // address of `scratch` on each device, once known
+}  // namespace
+
+hipError_t stats_scratch(double **ptr, size_t *doubles) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *ptr = scratch_dev[dev];
+    if (doubles) *doubles = kScratchDoubles;
+    return hipSuccess;
 }
 
 hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t s) {

@@ -101,6 +101,7 @@ _SIG = {
     "lbm_populations": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
     "lbm_set_populations": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
     "lbm_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(lbm_stats_t)]),
+    "lbm_stats_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(lbm_stats_t)]),
     "lbm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_timing": (ctypes.c_int, [_P, _D, _D, ctypes.POINTER(ctypes.c_longlong)]),
     "lbm_eos_critical": (ctypes.c_int, [ctypes.POINTER(lbm_eos), _D, _D, _D]),
@@ -257,6 +258,14 @@ class Lattice:
     def stats(self, track_dv=False, allow_unstable=False):
         s = lbm_stats_t()
         rc = lbm_stats(self.h, int(track_dv), ctypes.byref(s))
+        if rc != LBM_OK and not (allow_unstable and rc == LBM_EUNSTABLE):
+            check(rc, self.h)
+        return s.as_dict()
+
+    def stats_noalloc(self, allow_unstable=False):
+        """lbm_stats without allocating (the library's fixed device array; no dv)."""
+        s = lbm_stats_t()
+        rc = lbm_stats_noalloc(self.h, ctypes.byref(s))
         if rc != LBM_OK and not (allow_unstable and rc == LBM_EUNSTABLE):
             check(rc, self.h)
         return s.as_dict()
