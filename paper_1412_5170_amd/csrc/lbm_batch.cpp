@@ -41,7 +41,9 @@ struct lbm_batch {
     int2 *meta2 = nullptr;           //   first row, rows), and each kind's slice of it
     size_t max_tiles2 = 0;
     int rows2 = 24;                  // segment height of the two-step tiles, per upload
-    std::vector<int> kinds;          // kinds present (scheme * 2 + collision), ascending
+    std::vector<int> kind_tiles2;    // two-step tiles of each kind, per upload
+    std::vector<int> graph_tiles2;   // the same when the graph was captured (its grid sizes)
+    std::vector<int> kinds;          // kernel kinds present (pplbm::kernel_kind), ascending
     size_t max_tiles = 0;
     // observables
     int4 *sblocks = nullptr;
@@ -174,7 +176,7 @@ int upload_tiles(lbm_batch *b) {
         for (int i = 0; i < b->count; ++i) {
             if (!b->active[i]) continue;
             const Physics &p = b->phys[i];
-            if (p.scheme * 2 + p.coll != kind) continue;
+            if (pplbm::kernel_kind(p.scheme) != kind) continue;
             const int H = b->seg_rows[i] ? b->seg_rows[i] : b->auto_rows;
             for (int y0 = 0; y0 < p.ny; y0 += H)
                 for (int x0 = 0; x0 < p.nx; x0 += b->tx) t.push_back(make_int4(i, x0, y0, H));
@@ -208,12 +210,14 @@ int upload_tiles(lbm_batch *b) {
             for (int i = 0; i < b->count; ++i) {
                 if (!b->active[i]) continue;
                 const Physics &p = b->phys[i];
-                if (p.scheme * 2 + p.coll != kind) continue;
+                if (pplbm::kernel_kind(p.scheme) != kind) continue;
                 for (int y0 = 0; y0 < p.ny; y0 += b->rows2)
                     for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(make_int4(i, x0, y0, b->rows2));
             }
             meta2.push_back(make_int2(first, (int)t2.size() - first));
         }
+        b->kind_tiles2.clear();
+        for (const int2 &m : meta2) b->kind_tiles2.push_back(m.y);
         if (!t2.empty())
             BHIP(b, hipMemcpyAsync(b->tiles2, t2.data(), t2.size() * sizeof(int4), hipMemcpyHostToDevice,
                                    b->stream));
@@ -234,13 +238,12 @@ int grid_groups(const lbm_batch *b) {
     return (int)g;
 }
 
-// Workgroups (of four waves) of a two-step launch: one wave per tile up to 4096 waves, a
-// multiple of 8 (each XCD walks its own eighth of the tile list).
-int grid2_groups(const lbm_batch *b) {
-    size_t all = 0;
-    for (int i = 0; i < b->count; ++i) all += tiles2_at(b, i, kTwoStepRowsMin);
-    const size_t g = std::min<size_t>((all + 3) / 4, 1024);
-    return (int)std::max<size_t>((g + 7) / 8 * 8, 8);
+// Workgroups (of four waves) of a two-step launch of kind j: one wave per tile of the current
+// tile list, so the hardware hands tiles to free wave slots as they come.  The graph is
+// captured again whenever these counts change.
+int grid2_groups(const lbm_batch *b, size_t j) {
+    const int n = j < b->kind_tiles2.size() ? b->kind_tiles2[j] : 0;
+    return std::max(1, (n + 3) / 4);
 }
 
 // n (even) steps as launches: with two steps per launch, 2 (n / 4) two-step launches and the
@@ -254,7 +257,7 @@ void step_plan(const lbm_batch *b, int n, int *two, int *one) {
 hipError_t launch_kind(lbm_batch *b, size_t j, bool two, int parity, hipStream_t s) {
     if (two)
         return pplbm::launch_batch2_kind(b->desc, b->tiles2, b->meta2, (int)j, b->kinds[j] / 2,
-                                         b->kinds[j] % 2, parity, grid2_groups(b), s);
+                                         b->kinds[j] % 2, parity, grid2_groups(b, j), s);
     return pplbm::launch_batch_kind(b->desc, b->tiles, b->meta, (int)j, b->kinds[j] / 2,
                                     b->kinds[j] % 2, parity, b->tx, grid_groups(b),
                                     b->flags & pplbm::kFlagShallow, s);
@@ -310,7 +313,7 @@ int ensure_side_streams(lbm_batch *b) {
 }
 
 int ensure_graph(lbm_batch *b, int steps) {
-    if (b->graph && b->graph_steps == steps) return LBM_OK;
+    if (b->graph && b->graph_steps == steps && b->graph_tiles2 == b->kind_tiles2) return LBM_OK;
     drop_graph(b);
     const bool by_kind = b->kinds.size() > 1 && !(b->flags & LBM_LAUNCH_SERIAL_KINDS);
     if (by_kind) {
@@ -333,6 +336,7 @@ int ensure_graph(lbm_batch *b, int steps) {
         return bfail(b, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
     b->graph_steps = steps;
+    b->graph_tiles2 = b->kind_tiles2;
     return LBM_OK;
 }
 
@@ -367,7 +371,7 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
             return rc;
         }
     }
-    for (int i = 0; i < count; ++i) b->kinds.push_back(b->phys[i].scheme * 2 + b->phys[i].coll);
+    for (int i = 0; i < count; ++i) b->kinds.push_back(pplbm::kernel_kind(b->phys[i].scheme));
     std::sort(b->kinds.begin(), b->kinds.end());
     b->kinds.erase(std::unique(b->kinds.begin(), b->kinds.end()), b->kinds.end());
     b->f0.assign(count, nullptr);

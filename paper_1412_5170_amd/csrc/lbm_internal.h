@@ -36,6 +36,13 @@ struct Physics {
 };
 
 enum { kPrecF64 = 1, kPrecMixed = 2 };  // the values of LBM_PREC_*
+
+// The kernel a lattice runs, as scheme * 2 + collision: the exact-difference and Shan-Chen
+// schemes with BGK, Guo's schemes (with or without Li's term) with the moment-space collision
+// that serves BGK (every rate 1/tau) and MRT alike, so both collisions share one kernel.
+inline int kernel_kind(int scheme) {
+    return scheme == GUO || scheme == GUO_LI ? scheme * 2 + MRT : scheme * 2 + BGK;
+}
 constexpr int kFlagNT = 1;   // non-temporal stores of the new populations
 constexpr int kFlagXCD = 2;  // XCD-aware order of the tiles
 constexpr int kFlagShallow = 4;  // sweep: prefetch one row ahead instead of two

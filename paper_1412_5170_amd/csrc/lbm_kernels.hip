@@ -114,10 +114,9 @@ struct StepConst {
     D gA;     // -G A / 2        coefficient of sum w psi^2 e    (Eq. 6, U = G psi^2 / 2)
     D gB;     // -G (1 - A)      coefficient of psi(x) sum w psi e
     D omega;  // 1 / tau
-    D kguo;   // 1 - 1/(2 tau)   (Eq. 23)
-    R li;     // sigma / (tau - 1/2): v' = v + li F / psi^2 (Eq. 31)
-    R li2;    // 2 sigma: Li's extra stress X = li2 F F / psi^2 (MRT form)
-    D sd[9];  // MRT rates in moment order over the squared norms of M's rows (M^-1 = M^T D^-1)
+    R li2;    // 2 sigma: Li's extra stress X = li2 F F / psi^2 (Eq. 31 in moment space)
+    D sd[9];  // rates in moment order (all 1/tau for BGK) over the squared norms of M's rows
+              // (M^-1 = M^T D^-1)
     D hd[9];  // (1 - s/2) over the same norms
     R lim[9]; // 1 / (1/s_k - 1/2) for the moments that carry Li's stress
 
@@ -177,17 +176,6 @@ __device__ __forceinline__ R inv_sq(float pc) {
         return R(1) / (R(pc) * R(pc));
 }
 
-// Guo's bracket B_q = w_q [3 e.F + 9 (e.F)(e.V) - 3 F.V] (Eq. 23 with c_s^2 = 1/3).
-template <typename R>
-__device__ __forceinline__ void guo_bracket(R Fx, R Fy, R Vx, R Vy, R B[9]) {
-    const R FV = R(3) * (Fx * Vx + Fy * Vy);
-    B[0] = -wgt<R>(0) * FV;
-    const R eF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
-    const R eV[8] = {Vx, Vy, -Vx, -Vy, Vx + Vy, Vy - Vx, -Vx - Vy, Vx - Vy};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) B[1 + q] = wgt<R>(1 + q) * (R(3) * eF[q] + R(9) * eF[q] * eV[q] - FV);
-}
-
 // One node of the time step once psi is known around it: interaction force (Eq. 6), moments
 // and velocities (Sec. 3.2), forcing scheme and collision.  f holds the post-streaming
 // populations of the node; fs receives the post-collision ones (FP32, ready to store).
@@ -226,7 +214,7 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
     const R pc = p.c;
 
     D upd[9];  // f*_q - f_q
-    if constexpr (COLL == BGK) {
+    if constexpr (SCHEME == EDM || SCHEME == SC) {  // BGK only (lbm_create rejects MRT)
         D neq[9];
         if constexpr (SCHEME == EDM) {
             // Eq. 22 with f^eq(rho, u + D) - f^eq(rho, u) written out exactly:
@@ -248,21 +236,12 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
             eq_minus_f<R, D>(rho_d, ex, ey, f, neq);
 #pragma unroll
             for (int q = 0; q < 9; ++q) upd[q] = c.omega * neq[q];
-        } else {
-            // Eq. 23 (Guo) or Eq. 31 (Li): equilibrium at v, bracket at v or v'.
-            eq_minus_f<R, D>(rho_d, vx, vy, f, neq);
-            R bx = vx, by = vy;
-            if constexpr (SCHEME == GUO_LI) {
-                const R cl = c.li * inv_sq<R>(pc);
-                bx = vx + cl * Fx;
-                by = vy + cl * Fy;
-            }
-            R B[9];
-            guo_bracket<R>(Fx, Fy, bx, by, B);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) upd[q] = c.omega * neq[q] + c.kguo * (D)B[q];
         }
     } else {
+        // Guo's forcing (Eq. 23; Eq. 31 with Li's term) with the BGK collision (Eq. 1) or the
+        // MRT collision (Eq. 34), both in moment space: BGK is the MRT collision with every rate
+        // 1/tau (the rates lbm_create sets for BGK), which reproduces Eq. 1 with Eq. 23 or Eq. 31
+        // exactly and costs fewer instructions than the nine populations' equilibria.
         // MRT, Eq. 34: m* = m - Lambda (m - m_eq) + (I - Lambda/2) S with m_eq = M f^eq(rho, v).
         // Evaluated as f* = f + M^-1 [Lambda (m_eq - m) + (I - Lambda/2) S] so that only
         // non-equilibrium quantities go through the inverse transform.  m_eq has the closed form
@@ -297,23 +276,34 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
             S[7] += (Xxx - Xyy) * c.lim[7];
             S[8] += Xxy * c.lim[8];
         }
-        D a[9];  // D^-1 [Lambda (m_eq - m) + (I - Lambda/2) S]; row 0 vanishes (n_0 = S_0 = 0)
-        a[0] = D(0);
-#pragma unroll
-        for (int k = 1; k < 9; ++k) a[k] = c.sd[k] * n[k] + c.hd[k] * (D)S[k];
-        // M^-1 = M^T D^-1
-        const D c0 = a[0] - a[1] - D(2) * a[2];
-        const D c5 = a[0] + D(2) * a[1] + a[2];
+        // a = D^-1 [Lambda (m_eq - m) + (I - Lambda/2) S]; row 0 vanishes (n_0 = S_0 = 0).  The
+        // momentum rows are exactly F / 6 whatever s_j is (j* = j + F), and the other F-sized
+        // sources are taken in D, where F already is.
+        D a[9];
+        a[1] = c.sd[1] * n[1] + c.hd[1] * (D)S[1];
+        a[2] = c.sd[2] * n[2] + c.hd[2] * (D)S[2];
+        a[3] = Fxd * (D(1) / D(6));
+        a[4] = c.sd[4] * n[4] - c.hd[4] * Fxd;
+        a[5] = Fyd * (D(1) / D(6));
+        a[6] = c.sd[6] * n[6] - c.hd[6] * Fyd;
+        a[7] = c.sd[7] * n[7] + c.hd[7] * (D)S[7];
+        a[8] = c.sd[8] * n[8] + c.hd[8] * (D)S[8];
+        // M^-1 = M^T D^-1, the pairs of opposite velocities formed once
+        const D c0 = -a[1] - D(2) * a[2];
+        const D c5 = D(2) * a[1] + a[2];
         const D gx = a[3] - D(2) * a[4], gy = a[5] - D(2) * a[6];
         const D hx = a[3] + a[4], hy = a[5] + a[6];
-        upd[1] = c0 + gx + a[7];
-        upd[2] = c0 + gy - a[7];
-        upd[3] = c0 - gx + a[7];
-        upd[4] = c0 - gy - a[7];
-        upd[5] = c5 + hx + hy + a[8];
-        upd[6] = c5 - hx + hy - a[8];
-        upd[7] = c5 - hx - hy + a[8];
-        upd[8] = c5 + hx - hy - a[8];
+        const D ap = c0 + a[7], am = c0 - a[7];
+        const D bp = c5 + a[8], bm = c5 - a[8];
+        const D hsum = hx + hy, hdif = hx - hy;
+        upd[1] = ap + gx;
+        upd[3] = ap - gx;
+        upd[2] = am + gy;
+        upd[4] = am - gy;
+        upd[5] = bp + hsum;
+        upd[7] = bp - hsum;
+        upd[8] = bm + hdif;
+        upd[6] = bm - hdif;
     }
 #pragma unroll
     for (int q = 1; q < 9; ++q) fs[q] = (float)((D)f[q] + upd[q]);
@@ -870,29 +860,26 @@ batch_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict_
     }
 }
 
-// Two steps per launch for one kind of the batch: the waves walk the kind's slice meta2[kind]
-// of the two-step tile list (lattice, first output column, first row, rows), one 64-lane strip
-// of 58 output columns per tile (the single lattice's two-step sweep, tile by tile).
-// Workgroups are dealt round-robin to the eight XCDs (the grid is a multiple of 8): the waves
-// of XCD k walk the k-th eighth of the slice, so tiles that overlap (neighbouring strips and
-// segments of one lattice) are read through the same L2.
+// Two steps per launch for one kind of the batch: one wave per tile of the kind's slice
+// meta2[kind] of the two-step tile list (lattice, first output column, first row, rows), each a
+// 64-lane strip of 58 output columns (the single lattice's two-step sweep, tile by tile).  The
+// grid holds at least one wave per tile (waves past the slice's count, read from device memory,
+// return at once); workgroups are remapped so that each XCD takes a contiguous run of tiles,
+// and tiles that overlap (neighbouring strips and segments of one lattice) are read through the
+// same L2.
 template <int SCHEME, int COLL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 batch2_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict__ tiles,
                    const int2 *__restrict__ meta, int kind, int parity) {
     const int2 m = meta[kind];
-    const int wpg = blockDim.x >> 6;
-    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
-    const int begin = (int)((long long)m.y * xcd / 8), end = (int)((long long)m.y * (xcd + 1) / 8);
-    const int waves = per * wpg;
-    const int w = local * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int t = begin + w; t < end; t += waves) {
-        const int4 tl = tiles[m.x + t];
-        const BatchLattice &L = lats[tl.x];
-        const StepConst<float, double> c = L.c;
-        sweep2_tile<float, double, SCHEME, COLL, false>(L.f[parity], L.f[parity ^ 1], c, tl.y,
-                                                        tl.z, tl.w);
-    }
+    const int b = tile_id(blockIdx.x, gridDim.x, true);
+    const int t = b * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= m.y) return;  // whole waves
+    const int4 tl = tiles[m.x + t];
+    const BatchLattice &L = lats[tl.x];
+    const StepConst<float, double> c = L.c;
+    sweep2_tile<float, double, SCHEME, COLL, false>(L.f[parity], L.f[parity ^ 1], c, tl.y, tl.z,
+                                                    tl.w);
 }
 
 // FP64 observables of one node of a batch lattice; psi of the stencil recomputed from f.
@@ -1264,8 +1251,6 @@ StepConst<R, D> make_const(const Physics &p, int flags) {
     c.gA = (D)(-p.G * p.A / 2.0);
     c.gB = (D)(-p.G * (1.0 - p.A));
     c.omega = (D)(1.0 / p.tau);
-    c.kguo = (D)(1.0 - 1.0 / (2.0 * p.tau));
-    c.li = (R)(p.sigma / (p.tau - 0.5));
     c.li2 = (R)(2.0 * p.sigma);
     for (int k = 0; k < 9; ++k) {
         c.sd[k] = (D)(p.s[k] / kRowNorm[k]);
@@ -1279,25 +1264,21 @@ dim3 row_grid(int nx, int ny, int block) {
     return dim3((unsigned)((nx + block - 1) / block), (unsigned)(ny < 65535 ? ny : 65535));
 }
 
-// Instantiates KERNEL<R, D, scheme, collision EXTRA> for the run-time scheme and collision;
-// EXTRA is empty or a further template argument list starting with a comma.
+// Instantiates KERNEL<R, D, scheme, collision EXTRA> for the run-time scheme; EXTRA is empty or
+// a further template argument list starting with a comma.  The exact-difference and Shan-Chen
+// schemes are BGK only; Guo's schemes (with or without Li's term) run one kernel for both
+// collisions -- their collision is computed in moment space, BGK being every rate 1/tau -- which
+// is instantiated with COLL = MRT (kernel_kind in lbm_internal.h names the same grouping).
 #define PPLBM_DISPATCH_X(KERNEL, R, D, EXTRA, p, grid, block, lds, s, ...)                        \
     do {                                                                                        \
-        if ((p).coll == BGK) {                                                                  \
-            if ((p).scheme == EDM)                                                              \
-                hipLaunchKernelGGL((KERNEL<R, D, EDM, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
-            else if ((p).scheme == GUO)                                                         \
-                hipLaunchKernelGGL((KERNEL<R, D, GUO, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
-            else if ((p).scheme == SC)                                                          \
-                hipLaunchKernelGGL((KERNEL<R, D, SC, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);     \
-            else                                                                                \
-                hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__); \
-        } else {                                                                                \
-            if ((p).scheme == GUO)                                                              \
-                hipLaunchKernelGGL((KERNEL<R, D, GUO, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__);    \
-            else                                                                                \
-                hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__); \
-        }                                                                                       \
+        if ((p).scheme == EDM)                                                                  \
+            hipLaunchKernelGGL((KERNEL<R, D, EDM, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);        \
+        else if ((p).scheme == SC)                                                              \
+            hipLaunchKernelGGL((KERNEL<R, D, SC, BGK EXTRA>), grid, block, lds, s, __VA_ARGS__);         \
+        else if ((p).scheme == GUO)                                                             \
+            hipLaunchKernelGGL((KERNEL<R, D, GUO, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__);        \
+        else                                                                                    \
+            hipLaunchKernelGGL((KERNEL<R, D, GUO_LI, MRT EXTRA>), grid, block, lds, s, __VA_ARGS__);     \
     } while (0)
 #define PPLBM_NOEXTRA
 #define PPLBM_PF1 , 1
@@ -1516,8 +1497,6 @@ hipError_t launch_batch_kind(const void *lats, const int4 *tiles, const int2 *me
         hipLaunchKernelGGL((batch_kind_kernel<S, C, 2>), g, blk, lds, s, L, tiles, meta, kind, parity)
     switch (scheme * 2 + coll) {
     case EDM * 2 + BGK: PPLBM_KIND(EDM, BGK); break;
-    case GUO * 2 + BGK: PPLBM_KIND(GUO, BGK); break;
-    case GUO_LI * 2 + BGK: PPLBM_KIND(GUO_LI, BGK); break;
     case SC * 2 + BGK: PPLBM_KIND(SC, BGK); break;
     case GUO * 2 + MRT: PPLBM_KIND(GUO, MRT); break;
     case GUO_LI * 2 + MRT: PPLBM_KIND(GUO_LI, MRT); break;
@@ -1535,8 +1514,6 @@ hipError_t launch_batch2_kind(const void *lats, const int4 *tiles, const int2 *m
     hipLaunchKernelGGL((batch2_kind_kernel<S, C>), g, blk, 0, s, L, tiles, meta, kind, parity)
     switch (scheme * 2 + coll) {
     case EDM * 2 + BGK: PPLBM_KIND2(EDM, BGK); break;
-    case GUO * 2 + BGK: PPLBM_KIND2(GUO, BGK); break;
-    case GUO_LI * 2 + BGK: PPLBM_KIND2(GUO_LI, BGK); break;
     case SC * 2 + BGK: PPLBM_KIND2(SC, BGK); break;
     case GUO * 2 + MRT: PPLBM_KIND2(GUO, MRT); break;
     case GUO_LI * 2 + MRT: PPLBM_KIND2(GUO_LI, MRT); break;
