@@ -288,20 +288,19 @@ int lbm_batch_create(int count, const int *nx, const int *ny, const lbm_eos *eos
                      lbm_batch_t **out);
 void lbm_batch_destroy(lbm_batch_t *b);
 
-/* tx threads per workgroup (multiple of 64, <= 512), `groups` persistent workgroups per kind
- * (0: one per tile up to 2048; rounded down to a multiple of 8, each XCD walking its own eighth
- * of the tile list), flags LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW |
- * LBM_LAUNCH_SERIAL_KINDS | LBM_LAUNCH_TWO_STEP.  The kinds (forcing scheme and collision)
- * touch disjoint lattices, so by default the captured graph holds one independent chain of
- * launches per kind, which the
- * GPU may run side by side; LBM_LAUNCH_SERIAL_KINDS captures them one after another on the
- * batch's stream instead.  LBM_LAUNCH_TWO_STEP advances two steps per launch with the
- * single lattice's two-step sweep (64-lane strips of 58 output columns; segments of 6 to 24
- * rows, chosen at every change of the active set by the single lattice's rule applied to the
- * active lattices' total wave count; with
- * n = 2 mod 4 steps the last two are one-step launches).  Results are bitwise the same in every
- * case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP (the 64-lattice droplet
- * sweep to equilibrium: 54.5 s against 78.5 s with one step per launch). */
+/* Launch of the batch's one-step kernel: tx threads per workgroup (multiple of 64, <= 512),
+ * `groups` persistent workgroups per kernel kind (0: one per tile up to 2048; rounded down to a
+ * multiple of 8, each XCD walking its own eighth of the tile list); flags
+ * LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_SHALLOW | LBM_LAUNCH_SERIAL_KINDS | LBM_LAUNCH_TWO_STEP.
+ * A kernel kind is a forcing scheme: exact difference and Shan-Chen (BGK), Guo and Guo + Li
+ * (BGK and MRT lattices share one kernel, the collision being computed in moment space).  The
+ * captured graph holds one chain of launches, kind after kind, on the batch's stream
+ * (LBM_LAUNCH_SERIAL_KINDS is accepted and is the only behaviour).  LBM_LAUNCH_TWO_STEP
+ * advances two steps per launch with the single lattice's two-step sweep: one 64-lane wave per
+ * tile (a strip of 58 output columns over a segment of 6 to 24 rows, the height chosen at every
+ * change of the active set by the single lattice's rule applied to the active lattices' total
+ * wave count); with n = 2 mod 4 steps the last two are one-step launches.  Results are bitwise
+ * the same in every case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP. */
 int lbm_batch_set_launch(lbm_batch_t *b, int tx, int groups, int flags);
 
 /* Segment height (rows per tile) of lattice i; 0 (the default) is automatic: every time the

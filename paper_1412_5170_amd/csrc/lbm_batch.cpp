@@ -56,9 +56,6 @@ struct lbm_batch {
     // 256-column strips and two rows of loads in flight
     int tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP;
     hipStream_t stream = nullptr;
-    std::vector<hipStream_t> side;   // one more stream per kind beyond the first (capture only)
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> join;
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
     bool tiles_dirty = true;
@@ -78,9 +75,8 @@ int bfail(lbm_batch *b, int code, const std::string &m) {
         if (e_ != hipSuccess) return bfail(b, LBM_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Destroys the captured graph once no launch of it can still be running: a graph whose kinds
-// run as branches executes across streams of the runtime, and freeing it while a replay is in
-// flight (the autotuner alternates graphs of 2 and trial_steps steps back to back) is unsafe.
+// Destroys the captured graph once no launch of it can still be running (the autotuner
+// alternates graphs of 2 and trial_steps steps back to back).
 void drop_graph(lbm_batch *b) {
     if (!b->graph) return;
     (void)hipStreamSynchronize(b->stream);
@@ -273,56 +269,15 @@ int launch_steps(lbm_batch *b, int n) {
     return LBM_OK;
 }
 
-// The same launches as launch_steps, one chain per kind on its own stream: forked from and
-// joined back into the batch's stream, so that a capture records independent branches.
-// Every launch and the joins are issued even after an error, so the capture can be closed.
-int launch_steps_by_kind(lbm_batch *b, int n) {
-    const size_t nk = b->kinds.size();
-    hipError_t e = hipEventRecord(b->fork, b->stream);
-    for (size_t j = 1; j < nk; ++j) {
-        const hipError_t w = hipStreamWaitEvent(b->side[j - 1], b->fork, 0);
-        if (e == hipSuccess) e = w;
-    }
-    int two, one;
-    step_plan(b, n, &two, &one);
-    for (size_t j = 0; j < nk; ++j) {
-        hipStream_t s = j == 0 ? b->stream : b->side[j - 1];
-        for (int k = 0; k < two + one && e == hipSuccess; ++k) e = launch_kind(b, j, k < two, k & 1, s);
-    }
-    for (size_t j = 1; j < nk; ++j) {
-        hipError_t w = hipEventRecord(b->join[j - 1], b->side[j - 1]);
-        if (w == hipSuccess) w = hipStreamWaitEvent(b->stream, b->join[j - 1], 0);
-        if (e == hipSuccess) e = w;
-    }
-    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
-    return LBM_OK;
-}
-
-int ensure_side_streams(lbm_batch *b) {
-    const size_t need = b->kinds.size() > 0 ? b->kinds.size() - 1 : 0;
-    if (!b->fork) BHIP(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-    while (b->side.size() < need) {
-        hipStream_t s = nullptr;
-        hipEvent_t ev = nullptr;
-        BHIP(b, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));  // default priority
-        b->side.push_back(s);
-        BHIP(b, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        b->join.push_back(ev);
-    }
-    return LBM_OK;
-}
-
 int ensure_graph(lbm_batch *b, int steps) {
     if (b->graph && b->graph_steps == steps && b->graph_tiles2 == b->kind_tiles2) return LBM_OK;
     drop_graph(b);
-    const bool by_kind = b->kinds.size() > 1 && !(b->flags & LBM_LAUNCH_SERIAL_KINDS);
-    if (by_kind) {
-        int rc = ensure_side_streams(b);
-        if (rc) return rc;
-    }
+    // One chain of launches on the batch's stream.  (Capturing one chain per kind on side
+    // streams, so that the graph had independent branches, was dropped: replacing such a graph
+    // between replays was followed by a host segmentation fault inside lbm_batch_step.)
     hipGraph_t g = nullptr;
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int rc = by_kind ? launch_steps_by_kind(b, steps) : launch_steps(b, steps);
+    int rc = launch_steps(b, steps);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -429,9 +384,6 @@ void lbm_batch_destroy(lbm_batch_t *b) {
                     (void *)b->meta2, (void *)b->sblocks,
                     (void *)b->ranges, (void *)b->ids, (void *)b->partial, (void *)b->out})
         if (p) (void)hipFree(p);
-    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
-    for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
-    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

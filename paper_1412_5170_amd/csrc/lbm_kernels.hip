@@ -125,8 +125,11 @@ struct StepConst {
         // Eq. 33 in the shape precision R (FP32 in the mixed path): psi is stored in FP32.
         return (float)ss_psi<R>((R)rho, (R)inv_eps);
     }
+    // psi of a node from its populations.  psi is a relative quantity stored in FP32, so the
+    // density it is evaluated at is summed in R (FP32 in the mixed path); the collision forms
+    // its own density in D.
     __device__ __forceinline__ float psi_of(const float f[9]) const {
-        return psi_of_rho(density9<D>(f));
+        return psi_of_rho((D)density9<R>(f));
     }
 };
 
@@ -181,7 +184,7 @@ __device__ __forceinline__ R inv_sq(float pc) {
 // populations of the node; fs receives the post-collision ones (FP32, ready to store).
 template <typename R, typename D, int SCHEME, int COLL>
 __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
-                                        const StepConst<R, D> &c, float fs[9], D rho_d) {
+                                        const StepConst<R, D> &c, float fs[9]) {
     // Eq. 6 with w(1) = 1/3, w(2) = 1/12: link sums as differences of opposite pairs.  In D:
     // in the light phase u and F/(2 rho) nearly cancel in v, so F and u must be accurate.
     const D third = D(1) / D(3), twelfth = D(1) / D(12);
@@ -201,8 +204,13 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         Fyd += c.gA * s2y;
     }
 
-    // Eq. 3 (rho_d = density9<D>(f), passed in: the sweep has it from the node's psi),
-    // u = sum f e / rho, v = u + F / (2 rho).  Momentum from opposite-pair differences.
+    // Eq. 3 in D from the sums of opposite pairs, in density()'s order (sums of FP32 values
+    // in FP64 are exact, so any grouping gives the same density); u = sum f e / rho,
+    // v = u + F / (2 rho).  Momentum from opposite-pair differences.
+    const D f0 = f[0];
+    const D p13 = (D)f[1] + (D)f[3], p24 = (D)f[2] + (D)f[4];
+    const D p57 = (D)f[5] + (D)f[7], p68 = (D)f[6] + (D)f[8];
+    const D rho_d = ((f0 + p13) + p24) + (p57 + p68);
     const D jx = (((D)f[1] - (D)f[3]) + ((D)f[5] - (D)f[7])) + ((D)f[8] - (D)f[6]);
     const D jy = (((D)f[2] - (D)f[4]) + ((D)f[5] - (D)f[7])) + ((D)f[6] - (D)f[8]);
     const D inv = recip<D>(rho_d), hinv = D(0.5) * inv;
@@ -248,8 +256,7 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         // rho (1, -2 + 3 v.v, 1 - 3 v.v, v_x, -v_x, v_y, -v_y, v_x^2 - v_y^2, v_x v_y) of the
         // moments of Eq. 2; each difference is written on the populations' deviation from the
         // rest state, and rho v = j + F/2 fixes the momentum rows exactly.
-        const D f0 = f[0], ax = ((D)f[1] + (D)f[2]) + ((D)f[3] + (D)f[4]);
-        const D dg = ((D)f[5] + (D)f[6]) + ((D)f[7] + (D)f[8]);
+        const D ax = p13 + p24, dg = p57 + p68;
         const D d13 = (D)f[1] - (D)f[3], d24 = (D)f[2] - (D)f[4];
         const D rv2 = rho_d * (vxd * vxd + vyd * vyd);
         const D hFx = D(0.5) * Fxd, hFy = D(0.5) * Fyd;
@@ -261,8 +268,8 @@ __device__ __forceinline__ void collide(const float f[9], const Nb<float> &p,
         n[4] = (D(3) * d13 - D(2) * jx) - hFx;                 // q_x
         n[5] = hFy;                                            // j_y
         n[6] = (D(3) * d24 - D(2) * jy) - hFy;                 // q_y
-        n[7] = rho_d * ((vxd - vyd) * (vxd + vyd)) - (((D)f[1] + (D)f[3]) - ((D)f[2] + (D)f[4]));
-        n[8] = rho_d * (vxd * vyd) - (((D)f[5] + (D)f[7]) - ((D)f[6] + (D)f[8]));
+        n[7] = rho_d * ((vxd - vyd) * (vxd + vyd)) - (p13 - p24);
+        n[8] = rho_d * (vxd * vyd) - (p57 - p68);
         // Guo's source in moment space, S = M B(v).
         const R vF = vx * Fx + vy * Fy;
         R S[9] = {R(0), R(6) * vF, -R(6) * vF, Fx, -Fx, Fy, -Fy,
@@ -531,7 +538,7 @@ __global__ void __launch_bounds__(1024) fused_kernel(const float *__restrict__ f
                       tile[lc + W],     tile[lc - W],     tile[lc + W + 1],
                       tile[lc + W - 1], tile[lc - W - 1], tile[lc - W + 1]};
     float fs[9];
-    collide<R, D, SCHEME, COLL>(f, nb, c, fs, density9<D>(f));
+    collide<R, D, SCHEME, COLL>(f, nb, c, fs);
     stream_out<R, D>(fout, c, x, y, fs, c.flags & kFlagNT);
 }
 
@@ -585,16 +592,12 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
     const int ys = dir > 0 ? y0 : y1 - 1;
     auto row = [&](int k) { return wrapy(ys + dir * k); };
     float fa[9], fb[9], fc[9], hc[9];
-    D ra = D(0), rb = D(0);  // FP64 densities of rows fa and fb, kept from their psi
     {
         const int rm = row(-1), r0 = row(0), rp = row(1);
         if (active) bload9(rin(rm), vx, roff(rm), qs, fc);
         if (active) bload9(rin(r0), vx, roff(r0), qs, fa);
         if (active) slot(-1)[tx + 1] = c.psi_of(fc);
-        if (active) {
-            ra = density9<D>(fa);
-            slot(0)[tx + 1] = c.psi_of_rho(ra);
-        }
+        if (active) slot(0)[tx + 1] = c.psi_of(fa);
         if (PF == 2 && active) bload9(rin(rp), vx, roff(rp), qs, fb);
         if (halo) {
             bload9(rin(rm), vh, roff(rm), qs, hc);
@@ -628,10 +631,7 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
                 ahead[hslot] = c.psi_of(hc);
             }
         }
-        if (active) {
-            rb = density9<D>(fb);
-            ahead[tx + 1] = c.psi_of_rho(rb);
-        }
+        if (active) ahead[tx + 1] = c.psi_of(fb);
         __syncthreads();
         if (active) {
             const float *behind = slot(k - 1), *rc = slot(k);
@@ -640,14 +640,13 @@ __device__ __forceinline__ void sweep_tile(const float *__restrict__ fin, float 
             const Nb<float> nb = {rc[l], rc[l + 1], rc[l - 1], rn[l], rs[l],
                                   rn[l + 1], rn[l - 1], rs[l - 1], rs[l + 1]};
             float fs[9];
-            collide<R, D, SCHEME, COLL>(fa, nb, c, fs, ra);
+            collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
             if constexpr (BIG)
                 bstream_out_rows<R, D>(fout, c, x, row(k), fs, nt);
             else
                 bstream_out<R, D>(rout, c, x, row(k), fs, nt);
         }
         if (PF == 2 && halo && more) slot(k + 2)[hslot] = c.psi_of(hc);
-        ra = rb;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             fa[q] = fb[q];
@@ -734,33 +733,29 @@ __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
     // s-1, s, s+1 (pm, pc, pn)
     const int s0 = y0 - 2;
     float fa[9], fb[9], fc[9];
-    D ra, rb;
     load_row(s0 - 1, fc);
     float pm = c.psi_of(fc);
     load_row(s0, fa);
-    ra = density9<D>(fa);
-    float pc = c.psi_of_rho(ra);
+    float pc = c.psi_of(fa);
     load_row(s0 + 1, fb);
     // step t+1: the populations of row s-1 streamed so far (planes 0,1,3 from row s-1, planes
-    // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete (g) with its
-    // density, and psi of rows s-3 and s-2
+    // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete (g), and psi
+    // of rows s-3 and s-2
     float a0 = 0.f, a1 = 0.f, a3 = 0.f, b2 = 0.f, b5 = 0.f, b6 = 0.f, c2 = 0.f, c5 = 0.f,
           c6 = 0.f;
     float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    D r2 = D(0);
     float qm = 0.f, qc = 0.f;
     const int nrow = y1 - y0 + 4;
     for (int k = 0; k < nrow; ++k) {
         const int s = s0 + k;
         if (k + 1 < nrow) load_row(s + 2, fc);
-        rb = density9<D>(fb);
-        const float pn = c.psi_of_rho(rb);
+        const float pn = c.psi_of(fb);
         // step t, row s (right on lanes 1..62)
         float fs[9];
         {
             const Nb<float> nb = {pc, lane_above(pc), lane_below(pc), pn, pm,
                                   lane_above(pn), lane_below(pn), lane_below(pm), lane_above(pm)};
-            collide<R, D, SCHEME, COLL>(fa, nb, c, fs, ra);
+            collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
         }
         // stream along x between lanes; along y into the rows held in registers
         const float e1 = lane_below(fs[1]), e5 = lane_below(fs[5]), e8 = lane_below(fs[8]);
@@ -775,14 +770,13 @@ __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
         a0 = fs[0];
         a1 = e1;
         a3 = w3;
-        const D r1 = density9<D>(f1);
-        const float qn = c.psi_of_rho(r1);
+        const float qn = c.psi_of(f1);
         // step t+1, row s-2 (right on lanes 3..60)
         if (k >= 4) {
             const Nb<float> nb = {qc, lane_above(qc), lane_below(qc), qn, qm,
                                   lane_above(qn), lane_below(qn), lane_below(qm), lane_above(qm)};
             float fo[9];
-            collide<R, D, SCHEME, COLL>(g, nb, c, fo, r2);
+            collide<R, D, SCHEME, COLL>(g, nb, c, fo);
             if (out) {
                 if constexpr (BIG)
                     bstream_out_rows<R, D>(fout, c, x, wrapy(s - 2), fo, nt);
@@ -792,12 +786,10 @@ __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) g[q] = f1[q];
-        r2 = r1;
         qm = qc;
         qc = qn;
         pm = pc;
         pc = pn;
-        ra = rb;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             fa[q] = fb[q];

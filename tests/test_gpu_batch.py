@@ -49,10 +49,10 @@ def _single(L, m, steps, tx, rows):
 @pytest.mark.parametrize("tx,flags", [(128, 4), (64, 0), (256, 4), (256, 12), (128, 8), (256, 16),
                                       (128, 24)])
 def test_batch_members_match_single_lattices_bitwise(L, tx, flags):
-    """Five kinds (scheme, collision): by default one concurrent chain of launches per kind in
-    the captured graph, with LBM_LAUNCH_SERIAL_KINDS (8) one chain; with LBM_LAUNCH_TWO_STEP
-    (16) two steps per launch (24 steps: six two-step launches per kind); the graph is replayed
-    and every replay is checked."""
+    """Five members of three kernel kinds (exact difference; Guo; Guo + Li on BGK and MRT
+    lattices alike), captured as one chain of launches (LBM_LAUNCH_SERIAL_KINDS, 8, is accepted
+    and changes nothing); with LBM_LAUNCH_TWO_STEP (16) two steps per launch (24 steps: six
+    two-step launches per kind); the graph is replayed and every replay is checked."""
     say(f"[batch bitwise] tx {tx} flags {flags}")
     b = L.Batch(MEMBERS, tx=tx, flags=flags)
     for i, m in enumerate(MEMBERS):

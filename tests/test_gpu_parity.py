@@ -104,19 +104,28 @@ def test_parity_100_steps(L, case, prec):
 
 def test_sc_equals_edm_at_tau_one(L):
     """Sec. 4.2.1: the Shan-Chen velocity shift and the exact-difference method give the same
-    result at tau = 1 (f* = f^eq(rho, u + F/rho) in both); on the GPU they agree to rounding."""
+    result at tau = 1 (f* = f^eq(rho, u + F/rho) in both).  On the GPU the Shan-Chen run
+    matches the oracle's exact-difference run at the parity bar, and the two GPU schemes agree
+    to the rounding of two arithmetic paths on an FP32 state (for tau != 1 the same slab's gas
+    density differs between the schemes by tens of per cent)."""
     out = {}
+    wl = workload("slab_4x256_edm", scheme="EDM", tau=1.0)
     for scheme in ("SC", "EDM"):
-        wl = workload("slab_4x256_edm", scheme=scheme, tau=1.0)
-        lat = gpu_lattice(L, wl, PRECISIONS["mixed"])
+        lat = gpu_lattice(L, dict(wl, scheme=scheme), PRECISIONS["mixed"])
         lat.init(initial_density(wl))
-        lat.step(200)
+        lat.step(100)
         out[scheme] = lat.read()
     d_rho = np.max(np.abs(out["SC"][0] - out["EDM"][0]) / out["EDM"][0])
     d_v = np.max(np.abs(out["SC"][1] - out["EDM"][1])) / np.max(np.abs(out["EDM"][1]))
-    say(f"    SC vs EDM at tau = 1: rho {d_rho:.2e}  v {d_v:.2e}")
-    # two arithmetic paths with FP32 storage, each within 1e-5 of the FP64 oracle
-    assert d_rho < 1e-6 and d_v < 5e-5
+    p = oracle_params(wl)
+    fl = O.fields(p, O.step(p, O.init_feq(initial_density(wl)), 100))
+    e_rho, e_v = errors(*out["SC"], fl)
+    say(f"    SC vs EDM at tau = 1: rho {d_rho:.2e}  v {d_v:.2e}; SC vs the oracle's EDM: "
+        f"rho {e_rho:.2e}  v {e_v:.2e}")
+    assert e_rho < TOL and e_v < TOL
+    # each within 1e-5 of the oracle: the two GPU paths differ by less than the sum of their
+    # rounding errors
+    assert d_rho < 5e-6 and d_v < 2e-5
 
 
 @pytest.mark.parametrize("tile", [(64, 4), (128, 2), (64, 1)])
