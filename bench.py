@@ -45,13 +45,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public spec
 SWEEP_BYTES_PER_NODE = 72      # one-pass step: 9 FP32 populations read + 9 written
-# Floating-point operations of one node's update on this workload's path (C-S EOS, MRT with Guo
-# and Li, mixed precision), counted in the compiled update: 2 per FMA, 1 per add, multiply,
-# reciprocal or square root; conversions, moves and lane shifts count 0.
-FLOPS_PER_NODE_STEP = 236
-# Vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, for
-# FP64 and unpacked FP32 alike; and the VALU issue peak, 1024 SIMDs x 16 lanes x 2.4 GHz.
-ALU_PEAK_TFLOPS = 78.6
+# VALU issue peak: 1024 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second (one wave64
+# instruction per SIMD every four cycles; FP64 and unpacked FP32 issue alike).
 VALU_LANE_OPS_PEAK = 1024 * 16 * 2.4e9
 FUSED_BYTES_PER_NODE = 76      # two-pass, pass 2: 9 populations read + 9 written + psi read
 PSI_BYTES_PER_NODE = 40        # two-pass, pass 1: 9 populations read + psi written
@@ -249,7 +244,8 @@ def settle(lat, seconds, torch):
 def roofline(kernel, ev, launch, nodes, args):
     """HBM roofline of one launch of `kernel`: algorithmic bytes per launch over the average
     launch time (HIP events around the timed region's launches), against 8 TB/s; the real
-    traffic, VALU issue and vector-ALU flop rates beside it."""
+    traffic and the VALU issue rate (from the committed counters of the same source and launch)
+    beside it."""
     psi_ms, main_ms, nt = ev
     steps_per_launch = 2 if kernel == "sweep2" else 1  # the two-step sweep: 2 per launch
     avg = main_ms / 1e3 / (nt / steps_per_launch)     # per launch of the main kernel
@@ -263,10 +259,6 @@ def roofline(kernel, ev, launch, nodes, args):
          "bytes_per_node_step": per_node, "steps_per_launch": steps_per_launch,
          "algorithmic_bytes_per_launch": algo_bytes, "launches": int(nt // steps_per_launch),
          "avg_us": round(avg * 1e6, 2)}
-    tflops = FLOPS_PER_NODE_STEP * steps_per_launch * nodes / avg / 1e12
-    r["alu"] = {"achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
-                "flops_per_node_step": FLOPS_PER_NODE_STEP}
     if kernel == "two_pass":
         pavg = psi_ms / 1e3 / nt
         r["psi_pass"] = {"kernel": "psi_kernel", "avg_us": round(pavg * 1e6, 2),
@@ -279,6 +271,8 @@ def roofline(kernel, ev, launch, nodes, args):
                 and list(t[key].get("launch", [])) == list(launch)):
             r["traffic"] = t[key]["bytes_per_launch"]
             r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] / algo_bytes, 4)
+            # the same against one read and one write of the populations per launch
+            r["traffic_over_one_pass"] = round(t[key]["bytes_per_launch"] / (72 * nodes), 4)
             if "valu_insts_per_launch" in t[key]:  # wave instructions (SQ_INSTS_VALU)
                 lane_ops = 64 * t[key]["valu_insts_per_launch"] / avg
                 r["valu_issue"] = {"achieved": round(lane_ops / 1e12, 2),
@@ -310,7 +304,19 @@ def batch_leg(lbm, steps):
     dt = time.perf_counter() - t0
     nodes = sum(m["nx"] * m["ny"] for m in members)
     del b
-    return {"lattices": len(members), "nodes": nodes, "steps": steps,
+    extra = {}
+    if os.path.exists(PROFILE_TRAFFIC):
+        t = json.load(open(PROFILE_TRAFFIC)).get("batch64/batch2/mixed")
+        if t and t["kernel_sha256_16"] == kernel_source_hash() and t["nodes"] == nodes:
+            per_launch = 2 * dt / steps  # two steps per launch
+            lane_ops = 64 * t["valu_insts_per_launch"] / per_launch
+            extra = {"traffic_per_launch": t["bytes_per_launch"],
+                     "traffic_over_one_pass": round(t["bytes_per_launch"] / (72 * nodes), 4),
+                     "valu_issue": {"achieved": round(lane_ops / 1e12, 2),
+                                    "peak": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                                    "unit": "T lane-instructions/s",
+                                    "frac": round(lane_ops / VALU_LANE_OPS_PEAK, 4)}}
+    return {**extra, "lattices": len(members), "nodes": nodes, "steps": steps,
             "seconds": round(dt, 4), "us_per_step": round(dt / steps * 1e6, 2),
             "GLUPS": round(nodes * steps / dt / 1e9, 2),
             "hbm_algorithmic": {"achieved": round(72 * nodes * steps / dt / 1e9, 1),
