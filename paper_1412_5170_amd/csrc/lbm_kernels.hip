@@ -704,43 +704,58 @@ __device__ __forceinline__ float lane_above(float v) {  // lane i receives lane 
 constexpr int kSweep2Out = 58;  // output columns of a 64-lane strip (lanes 3..60)
 
 // One wave's tile: the strip whose first output column is xw (on lane 3), rows [y0, y0 + H)
-// (clipped at ny); xw, y0 and H are wave-uniform.
-template <typename R, typename D, int SCHEME, int COLL, bool BIG>
+// (clipped at ny); xw, y0 and H are wave-uniform.  DIR = +1 sweeps the rows upwards in y,
+// DIR = -1 downwards (the same per-node arithmetic on the same neighbours, so the same bits):
+// the tiles of a strip alternate, so that two neighbouring segments read the six rows they
+// share at the same end of their sweeps, at about the same time, and one of the two reads is
+// served by L2.
+template <typename R, typename D, int SCHEME, int COLL, bool BIG, int DIR>
 __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
                                             float *__restrict__ fout, const StepConst<R, D> &c,
                                             int xw, int y0, int H) {
+    static_assert(DIR == 1 || DIR == -1, "sweep direction");
     const int lane = threadIdx.x & 63;
     const int nx = c.nx, ny = c.ny;
     const int y1 = y0 + H < ny ? y0 + H : ny;
     auto wrapx = [&](int xx) { xx %= nx; return xx < 0 ? xx + nx : xx; };
-    auto wrapy = [&](int yy) { yy %= ny; return yy < 0 ? yy + ny : yy; };
+    // row r of the sweep (r = 0 is the first row of the segment in the sweep's order; wrapped)
+    const int base = DIR > 0 ? y0 : y1 - 1;
+    auto row = [&](int r) { int yy = (base + DIR * r) % ny; return yy < 0 ? yy + ny : yy; };
     const int x = wrapx(xw - 3 + lane);
     const bool out = lane >= 3 && lane < 3 + kSweep2Out && xw + lane - 3 < nx;
     const bool nt = c.flags & kFlagNT;
     const __amdgpu_buffer_rsrc_t rbuf = pop_rsrc(fin, c.fbytes), rout = pop_rsrc(fout, c.fbytes);
     const unsigned qs = 4u * (unsigned)c.fq, fr = 4u * (unsigned)c.frow;
     const unsigned vx = 4u * x;
-    // loads of row r (wrapped): the whole-buffer resource, or beyond 4 GiB the row's own
+    // loads of sweep row r: the whole-buffer resource, or beyond 4 GiB the row's own
     auto load_row = [&](int r, float v[9]) {
-        const int rr = wrapy(r);
+        const int rr = row(r);
         if constexpr (BIG)
             bload9(row_rsrc(fin, c.frow, c.ffloats, rr), vx, 0u, qs, v);
         else
             bload9(rbuf, vx, fr * rr, qs, v);
     };
+    // psi of a node's eight neighbours from the rows behind (pb), at (pc) and ahead of (pa) it
+    // in the sweep's order; lane i + 1 is the neighbour in +x
+    auto stencil = [&](float pc, float pa, float pb) {
+        const float pn = DIR > 0 ? pa : pb, ps = DIR > 0 ? pb : pa;
+        return Nb<float>{pc, lane_above(pc), lane_below(pc), pn, ps,
+                         lane_above(pn), lane_below(pn), lane_below(ps), lane_above(ps)};
+    };
 
-    // step t: populations of rows s (fa), s+1 (fb), s+2 (fc, loads in flight); psi of rows
-    // s-1, s, s+1 (pm, pc, pn)
-    const int s0 = y0 - 2;
+    // step t: populations of sweep rows s (fa), s+1 (fb), s+2 (fc, loads in flight); psi of
+    // rows s-1, s, s+1 (pm, pc, pn)
+    const int s0 = -2;
     float fa[9], fb[9], fc[9];
     load_row(s0 - 1, fc);
     float pm = c.psi_of(fc);
     load_row(s0, fa);
     float pc = c.psi_of(fa);
     load_row(s0 + 1, fb);
-    // step t+1: the populations of row s-1 streamed so far (planes 0,1,3 from row s-1, planes
-    // 2,5,6 from row s-2), planes 2,5,6 of row s (from row s-1), row s-2 complete (g), and psi
-    // of rows s-3 and s-2
+    // step t+1: the populations of row s-1 streamed so far -- planes 0, 1, 3 from row s-1; the
+    // three planes that move along the sweep (2, 5, 6 upwards, 4, 7, 8 downwards) from row s-2
+    // (b*) and, for row s, from row s-1 (c*) --, row s-2 complete (g), and psi of rows s-3 and
+    // s-2
     float a0 = 0.f, a1 = 0.f, a3 = 0.f, b2 = 0.f, b5 = 0.f, b6 = 0.f, c2 = 0.f, c5 = 0.f,
           c6 = 0.f;
     float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -752,36 +767,39 @@ __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
         const float pn = c.psi_of(fb);
         // step t, row s (right on lanes 1..62)
         float fs[9];
-        {
-            const Nb<float> nb = {pc, lane_above(pc), lane_below(pc), pn, pm,
-                                  lane_above(pn), lane_below(pn), lane_below(pm), lane_above(pm)};
-            collide<R, D, SCHEME, COLL>(fa, nb, c, fs);
-        }
+        collide<R, D, SCHEME, COLL>(fa, stencil(pc, pn, pm), c, fs);
         // stream along x between lanes; along y into the rows held in registers
         const float e1 = lane_below(fs[1]), e5 = lane_below(fs[5]), e8 = lane_below(fs[8]);
         const float w3 = lane_above(fs[3]), w6 = lane_above(fs[6]), w7 = lane_above(fs[7]);
-        float f1[9] = {a0, a1, b2, a3, fs[4], b5, b6, w7, e8};  // row s-1 of step t+1
+        float f1[9];  // row s-1 of step t+1
+        if constexpr (DIR > 0) {
+            const float r[9] = {a0, a1, b2, a3, fs[4], b5, b6, w7, e8};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) f1[q] = r[q];
+        } else {
+            const float r[9] = {a0, a1, fs[2], a3, b2, e5, w6, b5, b6};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) f1[q] = r[q];
+        }
         b2 = c2;
         b5 = c5;
         b6 = c6;
-        c2 = fs[2];
-        c5 = e5;
-        c6 = w6;
+        c2 = DIR > 0 ? fs[2] : fs[4];
+        c5 = DIR > 0 ? e5 : w7;
+        c6 = DIR > 0 ? w6 : e8;
         a0 = fs[0];
         a1 = e1;
         a3 = w3;
         const float qn = c.psi_of(f1);
         // step t+1, row s-2 (right on lanes 3..60)
         if (k >= 4) {
-            const Nb<float> nb = {qc, lane_above(qc), lane_below(qc), qn, qm,
-                                  lane_above(qn), lane_below(qn), lane_below(qm), lane_above(qm)};
             float fo[9];
-            collide<R, D, SCHEME, COLL>(g, nb, c, fo);
+            collide<R, D, SCHEME, COLL>(g, stencil(qc, qn, qm), c, fo);
             if (out) {
                 if constexpr (BIG)
-                    bstream_out_rows<R, D>(fout, c, x, wrapy(s - 2), fo, nt);
+                    bstream_out_rows<R, D>(fout, c, x, row(s - 2), fo, nt);
                 else
-                    bstream_out<R, D>(rout, c, x, wrapy(s - 2), fo, nt);
+                    bstream_out<R, D>(rout, c, x, row(s - 2), fo, nt);
             }
         }
 #pragma unroll
@@ -798,6 +816,18 @@ __device__ __forceinline__ void sweep2_tile(const float *__restrict__ fin,
     }
 }
 
+// The tile in the direction of its segment's parity (even segments upwards).
+template <typename R, typename D, int SCHEME, int COLL, bool BIG>
+__device__ __forceinline__ void sweep2_tile_alt(const float *__restrict__ fin,
+                                                float *__restrict__ fout,
+                                                const StepConst<R, D> &c, int xw, int y0, int H,
+                                                bool down) {
+    if (down)
+        sweep2_tile<R, D, SCHEME, COLL, BIG, -1>(fin, fout, c, xw, y0, H);
+    else
+        sweep2_tile<R, D, SCHEME, COLL, BIG, 1>(fin, fout, c, xw, y0, H);
+}
+
 template <typename R, typename D, int SCHEME, int COLL, bool BIG = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst<R, D> c, int H,
@@ -808,8 +838,9 @@ sweep2_kernel(const float *__restrict__ fin, float *__restrict__ fout, StepConst
     const int b = tile_id(blockIdx.x, gridDim.x, c.flags & kFlagXCD);
     const int t = b * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= ntiles) return;  // whole waves
-    sweep2_tile<R, D, SCHEME, COLL, BIG>(fin, fout, c, (t % nstrips) * kSweep2Out,
-                                         (t / nstrips) * H, H);
+    const int seg = t / nstrips;
+    sweep2_tile_alt<R, D, SCHEME, COLL, BIG>(fin, fout, c, (t % nstrips) * kSweep2Out, seg * H, H,
+                                             seg & 1);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -870,8 +901,8 @@ batch2_kind_kernel(const BatchLattice *__restrict__ lats, const int4 *__restrict
     const int4 tl = tiles[m.x + t];
     const BatchLattice &L = lats[tl.x];
     const StepConst<float, double> c = L.c;
-    sweep2_tile<float, double, SCHEME, COLL, false>(L.f[parity], L.f[parity ^ 1], c, tl.y, tl.z,
-                                                    tl.w);
+    sweep2_tile_alt<float, double, SCHEME, COLL, false>(L.f[parity], L.f[parity ^ 1], c, tl.y,
+                                                        tl.z, tl.w, (tl.z / tl.w) & 1);
 }
 
 // FP64 observables of one node of a batch lattice; psi of the stencil recomputed from f.
