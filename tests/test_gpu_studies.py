@@ -94,6 +94,35 @@ def test_bubble_tables_4_and_5(L, S):
     assert res[3]["rho_g"] < res[4]["rho_g"]
 
 
+def test_bubble_table_7_mrt(L, S):
+    """Table 7 (Sec. 4.4.2: the Table 4 bubble under MRT, tau_nu = 0.7, 1, 1.5) with the EOS scale
+    and the free rates the text leaves out taken as K = 0.5 and s_e = s_eps = s_q = 1: gas
+    density, peak spurious velocity and liquid density against the printed values, and the
+    section's claims that MRT shrinks tau's effect on the gas density and the spurious velocities
+    against BGK at the same parameters."""
+    say("[studies] bubbles, Table 7")
+    mrt = [dict(S.bubble_member("GUO", A=-0.84, K=S.TABLE7_K, tau=t, collision="MRT"),
+                s=S.TABLE7_RATES) for t in (0.7, 1.0, 1.5)]
+    bgk = [S.bubble_member("GUO", A=-0.84, K=S.TABLE7_K, tau=t) for t in (0.7, 1.0, 1.5)]
+    res = S.run(L, mrt + bgk, tol=1e-9, tol_rho=1e-9, check_every=500, max_steps=300_000)
+    for r in res:
+        assert r["status"] == 0, r
+    m, b = res[:3], res[3:]
+    for r, g in zip(m, GOLDEN["table7"]):
+        say(f"    table 7 tau {r['tau']}: rho_g {r['rho_g']:.6f} (paper {g['rho_g']}), Us "
+            f"{r['us_max']:.4f} ({g['us_max']}), rho_l {r['rho_l']:.5f} ({g['rho_l']})")
+        assert r["rho_g"] == pytest.approx(g["rho_g"], rel=0.05)
+        assert r["us_max"] == pytest.approx(g["us_max"], rel=0.15)
+        assert r["rho_l"] == pytest.approx(g["rho_l"], rel=0.006)
+    # the gas density falls with tau_nu, as printed, over less than half BGK's range
+    gm, gb = [r["rho_g"] for r in m], [r["rho_g"] for r in b]
+    assert gm[0] > gm[1] > gm[2]
+    assert gm[0] - gm[2] < 0.5 * (gb[0] - gb[2])
+    # smaller spurious velocities away from tau = 1, where the two collisions coincide
+    assert m[0]["us_max"] < 0.5 * b[0]["us_max"] and m[2]["us_max"] < 0.75 * b[2]["us_max"]
+    assert m[1]["rho_g"] == pytest.approx(b[1]["rho_g"], rel=1e-6)
+
+
 def test_eq33_flat_interface_is_thermodynamically_consistent(L, S):
     """Sec. 4.3.1: with psi of Eq. 33 and A = -eps/2 (Eq. 18 identical to Eq. 19) a flat
     interface settles at the Maxwell densities of the implied EOS, up to the higher-order
