@@ -445,7 +445,7 @@ int lbm_batch_init(lbm_batch_t *b, int i, const double *rho0, const double *u0) 
 
 namespace {
 // f0 of lattice i, holding f^eq(rho, 0), becomes the force-consistent rest state.
-int rest_state(lbm_batch *b, int i) {
+static int rest_state(lbm_batch *b, int i) {
     const Physics &p = b->phys[i];
     float *psi = nullptr;
     if (hipMalloc(&psi, p.plane * sizeof(float)) != hipSuccess) {
@@ -570,7 +570,7 @@ int lbm_batch_init_profile(lbm_batch_t *b, int i, const double *log_rho, double 
 }
 
 namespace {
-int size_class(const Physics &p) {  // ceil(log2(longer side))
+static int size_class(const Physics &p) {  // ceil(log2(longer side))
     int c = 0;
     while ((1 << c) < std::max(p.nx, p.ny)) ++c;
     return c;

@@ -34,6 +34,20 @@ def test_every_declared_symbol_is_exported(L):
     assert not missing, missing
 
 
+def test_no_undeclared_c_symbol_is_exported(L):
+    """Every unmangled function the library exports is one the header declares: helpers next
+    to the entry points keep internal linkage."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("needs nm")
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.split()[1:2] == ["T"]}
+    plain = {n for n in exported if not n.startswith("_")}
+    assert plain - set(declared_functions()) == set(), sorted(plain - set(declared_functions()))
+
+
 def test_critical_point_matches_oracle(L, thermo):
     rc, Tc, pc = L.eos_critical(L.make_eos(0.5))
     orc, oTc, opc = thermo.critical_point()
