@@ -274,10 +274,12 @@ int lbm_timing(lbm_t *h, double *psi_ms, double *fused_ms, long long *steps);
 /* ---- batched sweep ---------------------------------------------------------------------------
  * Many independent periodic lattices, each with its own size, EOS temperature and rescale,
  * force, collision and relaxation time (the parameter sweeps of Sec. 4 as one job), advanced
- * together: one persistent launch per time step walks a shared device list of tiles (strip of
- * tx columns x segment of rows of one lattice); blocks of steps are captured once in a hipGraph
- * and replayed; lattices that converge or go unstable are dropped from the tile list in device
- * memory between replays.  Per-node arithmetic is the single-lattice sweep's (mixed precision,
+ * together: by default one launch per kernel kind advances two time steps, one wave per tile
+ * of a shared device list of tiles (a 58-column strip x a segment of rows of one lattice; one
+ * step per launch walks a list of tx-column strips with persistent workgroups instead); blocks
+ * of steps are captured in a hipGraph and replayed; lattices that converge or go unstable are
+ * dropped from the tile lists in device memory between replays (the graph is captured again
+ * when a kind's tile count changes).  Per-node arithmetic is the single-lattice sweep's (mixed precision,
  * row-interleaved layout), so each lattice evolves bitwise as it would alone.  The batch owns
  * its device memory and a HIP stream of its own (default priority). */
 typedef struct lbm_batch lbm_batch_t;
