@@ -15,8 +15,9 @@ two-pass step, --autotune lets the library's autotuner pick, --launch sets the s
 `roofline` is the dominant kernel's HBM rate: algorithmic bytes per launch (72 B per node and
 time step: nine FP32 populations read and nine written, two time steps per launch of the
 two-step sweep) over the kernel's average launch time from HIP events on the lattice's stream,
-against 8 TB/s; the real traffic (rocprofv3 counters of the same source), the VALU issue rate
-and the vector-ALU flop rate stand beside it.
+against 8 TB/s (two steps per launch can pass 1: each launch reads and writes the populations
+once for two steps); the real traffic (rocprofv3 counters of the same source and launch), the
+HBM bandwidth it draws and the VALU issue rate stand beside it.
 
 Further legs (each can be switched off): the same for the alternative kernel; `batch`, the
 64-lattice droplet draw of the batched sweep (sizes 128^2-1024^2) stepped a fixed number of
@@ -68,7 +69,8 @@ def parse():
                     help="tx,ty[,flags] of the kernel (default: the library's choice)")
     ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
     ap.add_argument("--alt-steps", type=int, default=200,
-                    help="steps of the two-pass variant timed beside the main result (0: skip)")
+                    help="steps of the alternative kernel (the one-step sweep beside the two-step "
+                         "one) timed beside the main result (0: skip)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-every", type=int, default=100)
     ap.add_argument("--settle-seconds", type=float, default=2.0,
@@ -273,6 +275,9 @@ def roofline(kernel, ev, launch, nodes, args):
             r["traffic_over_algorithmic"] = round(t[key]["bytes_per_launch"] / algo_bytes, 4)
             # the same against one read and one write of the populations per launch
             r["traffic_over_one_pass"] = round(t[key]["bytes_per_launch"] / (72 * nodes), 4)
+            # the HBM bandwidth actually drawn: measured bytes over the same launch time
+            r["traffic_achieved"] = round(t[key]["bytes_per_launch"] / avg / 1e9, 1)
+            r["traffic_frac"] = round(t[key]["bytes_per_launch"] / avg / 1e9 / HBM_PEAK_GBS, 4)
             if "valu_insts_per_launch" in t[key]:  # wave instructions (SQ_INSTS_VALU)
                 lane_ops = 64 * t[key]["valu_insts_per_launch"] / avg
                 r["valu_issue"] = {"achieved": round(lane_ops / 1e12, 2),
