@@ -316,11 +316,11 @@ def evaluate(lbm, sur, members, tol, tol_rho, check_every=500, max_steps=1_500_0
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-count", type=int, default=2000)
-    ap.add_argument("--train-tol", type=float, default=1e-8)
-    ap.add_argument("--train-tol-rho", type=float, default=1e-8)
+    ap.add_argument("--train-tol", type=float, default=1e-9)
+    ap.add_argument("--train-tol-rho", type=float, default=2e-9)
     ap.add_argument("--train-levels", type=int, default=19, help="sizes 96 + 16 k, k < levels")
-    ap.add_argument("--train-steps", type=int, default=20000)
-    ap.add_argument("--train-large-count", type=int, default=0,
+    ap.add_argument("--train-steps", type=int, default=100000)
+    ap.add_argument("--train-large-count", type=int, default=64,
                     help="extra training droplets of sizes 512 + 16 k, k < 33 (the sweep's largest)")
     ap.add_argument("--eval-seed", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=64)

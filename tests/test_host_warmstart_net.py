@@ -27,6 +27,12 @@ def test_network_file_and_manifest():
     assert man["generation"][0]["converged"] == man["generation"][0]["members"]
     draw = WS.draw_training(man["training_draw"]["seed"], man["training_draw"]["count"])
     assert min(m["nx"] for m in draw) >= 96 and max(m["nx"] for m in draw) <= 384
+    # the droplets of the sweep's largest sizes, so that large radii are not extrapolated
+    large = WS.draw_training(man["large_draw"]["seed"], man["large_draw"]["count"], n_min=512,
+                             n_levels=33)
+    assert min(m["nx"] for m in large) >= 512 and max(m["nx"] for m in large) <= 1024
+    assert man["generation"][1]["members"] == len(large)
+    assert man["generation"][0]["tol"] == man["training_draw"]["stopping_rule"]["tol_velocity_per_step"]
 
 
 def test_predicted_profiles_are_physical():
