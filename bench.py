@@ -459,13 +459,13 @@ def main():
     if args.batch_steps:
         out["batch"] = batch_leg(lbm, args.batch_steps)
         say(f"batch: {out['batch']['GLUPS']} GLUPS, {out['batch']['us_per_step']} us per step")
-    if not args.no_sweep:
-        # the library's Python helpers report progress on stdout; the JSON line stays alone there
-        with contextlib.redirect_stdout(sys.stderr):
+    # the library's Python helpers report progress on stdout; the JSON line stays alone there
+    with contextlib.redirect_stdout(sys.stderr):
+        if not args.no_sweep:
             out["sweep"] = sweep_leg(lbm)
             say(f"sweep to equilibrium: {out['sweep']['wall_s']} s")
-            if not args.no_warm_start:
-                out["warm_start"] = warm_start_leg(lbm)
+        if not args.no_warm_start:
+            out["warm_start"] = warm_start_leg(lbm)
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

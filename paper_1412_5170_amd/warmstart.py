@@ -52,13 +52,15 @@ def features(m):
                      / (0.5 * math.log(K_RANGE[1] / K_RANGE[0]))], dtype=np.float32)
 
 
-def draw_training(seed, count, n_min=96, n_step=16, n_levels=19):
-    """Training droplets drawn like the sweep, with K log-uniform in K_RANGE."""
+def draw_training(seed, count, n_min=96, n_step=16, n_levels=19, K=None):
+    """Training droplets drawn like the sweep, with K log-uniform in K_RANGE (or every member
+    at the given K)."""
     draw = inputs.batch_draw(seed, count=count, n_min=n_min, n_step=n_step, n_levels=n_levels)
     rng = np.random.default_rng(seed + 7919)
     ms = sweep.members_from_draw(draw)
     for m in ms:
-        m["K"] = float(math.exp(rng.uniform(math.log(K_RANGE[0]), math.log(K_RANGE[1]))))
+        m["K"] = float(K) if K is not None else float(
+            math.exp(rng.uniform(math.log(K_RANGE[0]), math.log(K_RANGE[1]))))
     return ms
 
 
@@ -320,8 +322,13 @@ def main(argv=None):
     ap.add_argument("--train-tol-rho", type=float, default=2e-9)
     ap.add_argument("--train-levels", type=int, default=19, help="sizes 96 + 16 k, k < levels")
     ap.add_argument("--train-steps", type=int, default=100000)
+    ap.add_argument("--train-seed", type=int, default=0,
+                    help="seed of the validation split and the minibatch draws")
     ap.add_argument("--train-large-count", type=int, default=64,
                     help="extra training droplets of sizes 512 + 16 k, k < 33 (the sweep's largest)")
+    ap.add_argument("--train-sweep-k-count", type=int, default=0,
+                    help="extra training droplets of sizes 384 + 16 k, k < 41, all at the sweep's "
+                         "own K (seed 3)")
     ap.add_argument("--eval-seed", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=64)
     ap.add_argument("--eval-levels", type=int, default=57, help="sizes 128 + 16 k, k < levels")
@@ -355,6 +362,9 @@ def main(argv=None):
         draws = [] if a.data else [draw_training(1, a.train_count, n_levels=a.train_levels)]
         if a.train_large_count > 0:
             draws.append(draw_training(2, a.train_large_count, n_min=512, n_levels=33))
+        if a.train_sweep_k_count > 0:
+            draws.append(draw_training(3, a.train_sweep_k_count, n_min=384, n_levels=41,
+                                       K=sweep.PHYSICS["K"]))
         for tr in draws:
             t0 = time.perf_counter()
             prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
@@ -370,7 +380,7 @@ def main(argv=None):
         if a.out and draws:
             np.savez(a.out.replace(".json", "") + "_data.npz", X=X, Y=Y)
         t0 = time.perf_counter()
-        out["training"] = sur.fit(X, Y, steps=a.train_steps)
+        out["training"] = sur.fit(X, Y, steps=a.train_steps, seed=a.train_seed)
         out["training"]["wall_s"] = round(time.perf_counter() - t0, 1)
         if a.save_net:
             np.savez(a.save_net, params=sur.net.get_params(), mean=sur.mean, std=sur.std)

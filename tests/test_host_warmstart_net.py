@@ -32,6 +32,12 @@ def test_network_file_and_manifest():
                              n_levels=33)
     assert min(m["nx"] for m in large) >= 512 and max(m["nx"] for m in large) <= 1024
     assert man["generation"][1]["members"] == len(large)
+    # and droplets of the upper sizes at the sweep's own K, the value the sweep is run at
+    at_k = WS.draw_training(man["sweep_k_draw"]["seed"], man["sweep_k_draw"]["count"], n_min=384,
+                            n_levels=41, K=sweep.PHYSICS["K"])
+    assert min(m["nx"] for m in at_k) >= 384 and max(m["nx"] for m in at_k) <= 1024
+    assert all(m["K"] == sweep.PHYSICS["K"] for m in at_k)
+    assert man["generation"][2]["members"] == len(at_k)
     assert man["generation"][0]["tol"] == man["training_draw"]["stopping_rule"]["tol_velocity_per_step"]
 
 
