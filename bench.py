@@ -19,7 +19,9 @@ against 8 TB/s (two steps per launch can pass 1: each launch reads and writes th
 once for two steps); the real traffic (rocprofv3 counters of the same source and launch), the
 HBM bandwidth it draws and the VALU issue rate stand beside it.
 
-Further legs (each can be switched off): the same for the alternative kernel; `batch`, the
+Further legs (each can be switched off): the same for the alternative kernel; `small_configs`,
+the 4 x 256 EDM slab (microseconds per step, as a lone lattice and replayed from a hipGraph as a
+one-member batch) and the 512 x 512 Li droplet at tau 0.6 and 1.0 (MLUPS); `batch`, the
 64-lattice droplet draw of the batched sweep (sizes 128^2-1024^2) stepped a fixed number of
 steps (GLUPS); `sweep`, that draw run to equilibrium from tanh starts (max |v| change per step
 < 1e-9 and probe densities changing < 2e-9 per step, checked every 500 steps): wall time and
@@ -81,6 +83,8 @@ def parse():
                     help="skip the time-to-equilibrium legs (sweep and warm start)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-workload leg (4 x 256 slab, 512 x 512 droplet)")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel HIP events (for profiler runs)")
     return ap.parse_args()
@@ -329,6 +333,62 @@ def batch_leg(lbm, steps):
                                 "frac": round(72 * nodes * steps / dt / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def small_configs_leg(lbm, args, torch):
+    """The two small workloads, bound by launch latency or cache-resident, so no roofline: the
+    4 x 256 flat slab (EDM, BGK, tau = 1, T/Tc = 0.8, K = 1, A = -0.26; liquid rows 64-191 at
+    the Maxwell densities) for 10 000 steps, as a lone lattice (one launch per two steps) and as
+    a one-member batch (blocks of 100 steps replayed from a captured hipGraph): microseconds per
+    step; the 512 x 512 Li droplet (Guo + Li, BGK, T/Tc = 0.6, K = 1/49, R = 80) at tau = 0.6 and
+    1.0 for 20 000 steps: MLUPS.  Each after an untimed block of the same launches."""
+    from paper_1412_5170_amd import inputs
+
+    def lattice(wl):  # the library's default launch on each lattice
+        eos = lbm.make_eos(wl["T_over_Tc"], K=wl["K"])
+        g, l = lbm.eos_maxwell(eos)
+        rho0 = inputs.initial_density(wl, l, g)
+        lat = lbm.Lattice(wl["nx"], wl["ny"], eos,
+                          lbm.make_force(wl["scheme"], A=wl["A"], sigma=wl["sigma"]),
+                          lbm.make_collision(wl["collision"]), wl["tau"],
+                          precision=PRECISIONS[args.precision])
+        lat.init(rho0)
+        return lat, rho0
+
+    def wall(run, n):
+        run(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(n)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    slab = dict(inputs.WORKLOADS["slab_4x256_edm"])
+    n1 = 10_000
+    lat, rho0 = lattice(slab)
+    t_lone = wall(lat.step, n1)
+    del lat
+    b = lbm.Batch([dict(slab)])
+    b.init(0, rho0)
+
+    def batch_run(n):
+        for _ in range(n // 100):
+            b.step(100)
+        b.sync()
+
+    t_graph = wall(batch_run, n1)
+    del b
+    out = {"slab_4x256_edm": {"steps": n1, "lone_us_per_step": round(t_lone / n1 * 1e6, 3),
+                               "graph_us_per_step": round(t_graph / n1 * 1e6, 3)}}
+    n2 = 20_000
+    for tau in (0.6, 1.0):
+        wl = dict(inputs.WORKLOADS["droplet_512_li"], tau=tau)
+        lat, _ = lattice(wl)
+        dt = wall(lat.step, n2)
+        del lat
+        out[f"droplet_512_li_tau{tau}"] = {"steps": n2, "us_per_step": round(dt / n2 * 1e6, 3),
+                                           "MLUPS": round(wl["nx"] * wl["ny"] * n2 / dt / 1e6, 1)}
+    return out
+
+
 def sweep_leg(lbm):
     """Time to equilibrium of the 64-lattice draw from tanh starts (the batched sweep's own
     stopping rule)."""
@@ -456,6 +516,9 @@ def main():
                               "roofline": roofline(alt, ev2, alt_launch, nodes, args)}
     del rho0
     torch.cuda.empty_cache()
+    if not args.no_small:
+        out["small_configs"] = small_configs_leg(lbm, args, torch)
+        say(f"small configs: {json.dumps(out['small_configs'])}")
     if args.batch_steps:
         out["batch"] = batch_leg(lbm, args.batch_steps)
         say(f"batch: {out['batch']['GLUPS']} GLUPS, {out['batch']['us_per_step']} us per step")

@@ -164,7 +164,9 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, LBM_LAUNCH_XCD_ORDER) on every lattice,
  * with S = ceil(nx / 58) strips: ty = 16 where S * ceil(ny / 16) >= 8192 (from about 3000^2), else
  * ty = 24 where S * ceil(ny / 24) >= 3072 (about 2048^2), else the ty between 6 and 24 that
- * gives about 3200 waves.  The odd last step of an lbm_step call runs the one-step sweep with
+ * gives about 3200 waves; where that is 6 and ceil(S * ny / 1024) is below 6 (lattices up to
+ * about 512^2, whose launches are bound by each wave's chain of rows), ty = ceil(S * ny / 1024)
+ * and tx = 64.  The odd last step of an lbm_step call runs the one-step sweep with
  * tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then
  * ty) on small lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass
@@ -250,8 +252,8 @@ int lbm_stats_noalloc(lbm_t *h, lbm_stats_t *out);
 /* Autotuner: times trial_steps steps (rounded up to even) of the one-pass sweep for strip widths
  * tx in {64, 128, 256, 512}, segment heights ty in {4, 8, 16, 32, 64} and the flag sets
  * XCD|SHALLOW, SHALLOW, XCD, XCD|SHALLOW|NONTEMPORAL, and of the two-step sweep for tx in
- * {64, 128, 256}, ty in {6, 8, 12, 16, 24, 32} and the flags XCD or none; a planes-layout
- * lattice beyond 4 GiB, where neither sweep runs, tries the two-pass step for tx in
+ * {64, 128, 256}, ty in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32} and the flags XCD or none; a
+ * planes-layout lattice beyond 4 GiB, where neither sweep runs, tries the two-pass step for tx in
  * {64, 128, 256} and ty in {2, 4, 8} (tx * ty <= 1024) with LBM_LAUNCH_XCD_ORDER.  Shapes are
  * bitwise equivalent, so only speed differs.  Keeps the fastest and applies it with
  * lbm_set_launch.  Runs on the current state, which it saves and

@@ -371,7 +371,11 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     // slower); on smaller lattices the height that gives about 3200 waves, one resident round,
     // but at least 6 rows, below which the recomputed rows of step t cost more than the extra
     // waves gain (512^2: +14 %, 768^2: +21 %, 1024^2: +13 %, 1536^2: +7 % over the one-step
-    // sweep).  The one-step sweep's default shape serves the odd last step.
+    // sweep) -- except on lattices so small that 6 rows leave the GPU mostly idle: there each
+    // wave's chain of rows sets the time, and the height falls to about one wave per 1024 rows
+    // of strips (at least 1), one wave per workgroup (us per step against 6 rows: 4 x 256 slab
+    // 3.85 vs 9.02, 128^2 3.81 vs 7.16, 256^2 4.62 vs 7.35, 384^2 5.51 vs 7.47, 512^2 at 5 rows;
+    // 768^2 keeps 6).  The one-step sweep's default shape serves the odd last step.
     h->launch = default_launch(nx, ny);
     {
         const long long X = nx, Y = ny, strips = (X + 57) / 58;
@@ -385,6 +389,11 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
         } else {
             const long long segs = std::max(1LL, 3200 / strips);
             h->launch.ty = (int)std::min(24LL, std::max(6LL, (Y + segs - 1) / segs));
+            const long long small = std::max(1LL, (strips * Y + 1023) / 1024);
+            if (h->launch.ty == 6 && small < 6) {
+                h->launch.ty = (int)small;
+                h->launch.tx = 64;
+            }
         }
     }
     *out = h;
@@ -713,7 +722,7 @@ int lbm_autotune(lbm_t *h, const char *cache_path, int trial_steps, double *ms_o
             }
         }
         for (int tx : {64, 128, 256})  // two steps per launch
-            for (int ty : {6, 8, 12, 16, 24, 32})
+            for (int ty : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
                 for (int fl : {pplbm::kFlagXCD, 0}) {
                     if (he != hipSuccess || rc) break;
                     if (ty > 6 && ty / 2 >= h->p.ny) continue;

@@ -97,7 +97,7 @@ size_t tiles_max(const lbm_batch *b, int i) {
     return tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : kAutoRowsMin);
 }
 
-constexpr int kTwoStepRowsMin = 6;  // lowest segment height of the two-step tiles
+constexpr int kTwoStepRowsMin = 6;  // lowest segment height of the rule on larger batches
 
 size_t tiles2_at(const lbm_batch *b, int i, int rows) {
     const Physics &p = b->phys[i];
@@ -108,8 +108,10 @@ size_t tiles2_at(const lbm_batch *b, int i, int rows) {
 // Segment height of the two-step tiles of the active lattices, by the single lattice's rule
 // on the total wave count (the kinds run side by side): 16 rows where that makes at least 8192
 // waves, else 24 where that makes about 3072, else the lowest height from 6 rows up that makes
-// at most about 3200 (one resident round).  As converged lattices leave, the ones still
-// running are cut into shorter segments, so the last few still spread over the GPU.
+// at most about 3200 (one resident round); where even 6 rows leave fewer, the launch is bound
+// by the latency of each wave's rows and the height falls to about one wave per 1024 rows of
+// strips (at least 1).  As converged lattices leave, the ones still running are cut into
+// shorter segments, so the last few still spread over the GPU.
 int two_step_rows(const lbm_batch *b) {
     auto count = [&](int rows) {
         size_t n = 0;
@@ -120,7 +122,11 @@ int two_step_rows(const lbm_batch *b) {
     if (count(16) >= 8192) return 16;
     if (count(24) >= 3072) return 24;
     for (int rows = kTwoStepRowsMin; rows < 24; ++rows)
-        if (count(rows) <= 3200) return rows;
+        if (count(rows) <= 3200) {
+            if (rows == kTwoStepRowsMin)
+                return (int)std::min<size_t>(rows, std::max<size_t>(1, (count(1) + 1023) / 1024));
+            return rows;
+        }
     return 24;
 }
 
@@ -186,8 +192,10 @@ int upload_tiles(lbm_batch *b) {
     std::vector<int4> t2;
     std::vector<int2> meta2;
     if (two_step(b)) {
+        b->rows2 = two_step_rows(b);
         size_t need2 = 0;
-        for (int i = 0; i < b->count; ++i) need2 += tiles2_at(b, i, kTwoStepRowsMin);
+        for (int i = 0; i < b->count; ++i)
+            if (b->active[i]) need2 += tiles2_at(b, i, b->rows2);
         if (need2 > b->max_tiles2) {
             drop_graph(b);
             if (b->tiles2) (void)hipFree(b->tiles2);
@@ -200,7 +208,6 @@ int upload_tiles(lbm_batch *b) {
             b->max_tiles2 = need2;
         }
         const int w = pplbm::sweep2_out_columns();
-        b->rows2 = two_step_rows(b);
         for (int kind : b->kinds) {
             const int first = (int)t2.size();
             for (int i = 0; i < b->count; ++i) {

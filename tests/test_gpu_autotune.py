@@ -42,7 +42,7 @@ def test_single_autotune_restores_state_and_caches(L, tmp_path):
     assert a.stats()["step"] == 10
     k, tx, ty, fl = a.get_launch()
     assert ((k == L.LBM_KERNEL_SWEEP and tx in (64, 128, 256, 512) and ty in (4, 8, 16, 32, 64))
-            or (k == L.LBM_KERNEL_SWEEP2 and tx in (64, 128, 256) and ty in (6, 8, 12, 16, 24, 32)))
+            or (k == L.LBM_KERNEL_SWEEP2 and tx in (64, 128, 256) and ty in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)))
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     rec = json.loads(lines[0])
