@@ -164,9 +164,10 @@ int lbm_strides(const lbm_t *h, size_t *row_stride, size_t *velocity_stride);
  * the two-step sweep (LBM_KERNEL_SWEEP2, tx = 256, LBM_LAUNCH_XCD_ORDER) on every lattice,
  * with S = ceil(nx / 58) strips: ty = 16 where S * ceil(ny / 16) >= 8192 (from about 3000^2), else
  * ty = 24 where S * ceil(ny / 24) >= 3072 (about 2048^2), else the ty between 6 and 24 that
- * gives about 3200 waves; where that is 6 and ceil(S * ny / 1024) is below 6 (lattices up to
- * about 512^2, whose launches are bound by each wave's chain of rows), ty = ceil(S * ny / 1024)
- * and tx = 64.  The odd last step of an lbm_step call runs the one-step sweep with
+ * gives about 3200 waves; where that is 6 (lattices up to about 1024^2, too small to fill the
+ * GPU), tx = 64 and the ty in 1..12 that minimises (ty + 4) max(1.5, ceil(W / 1024)), W =
+ * S * ceil(ny / ty) waves: rows per wave times waves per SIMD.  The odd last step of an
+ * lbm_step call runs the one-step sweep with
  * tx = 512, ty = 8, two rows of loads in flight and LBM_LAUNCH_XCD_ORDER, narrowed (tx, then
  * ty) on small lattices until the launch has about 1024 workgroups.
  *   LBM_KERNEL_TWO_PASS: the density/psi pass writes psi, then the fused pass

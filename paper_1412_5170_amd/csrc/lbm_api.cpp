@@ -371,30 +371,21 @@ int lbm_create(int nx, int ny, const lbm_eos *eos, const lbm_force *force,
     // slower); on smaller lattices the height that gives about 3200 waves, one resident round,
     // but at least 6 rows, below which the recomputed rows of step t cost more than the extra
     // waves gain (512^2: +14 %, 768^2: +21 %, 1024^2: +13 %, 1536^2: +7 % over the one-step
-    // sweep) -- except on lattices so small that 6 rows leave the GPU mostly idle: there each
-    // wave's chain of rows sets the time, and the height falls to about one wave per 1024 rows
-    // of strips (at least 1), one wave per workgroup (us per step against 6 rows: 4 x 256 slab
-    // 3.85 vs 9.02, 128^2 3.81 vs 7.16, 256^2 4.62 vs 7.35, 384^2 5.51 vs 7.47, 512^2 at 5 rows;
-    // 768^2 keeps 6).  The one-step sweep's default shape serves the odd last step.
+    // sweep) -- except where 6 rows leave the GPU partly idle (lattices up to about 1024^2):
+    // there the busiest SIMD sets the time, and two_step_height picks 1-12 rows by its waves per
+    // SIMD and rows per wave, one wave per workgroup (us per step against 6 rows: 4 x 256 slab
+    // 3.85 vs 9.02, 128^2 3.81 vs 7.16, 256^2 4.62 vs 7.35, 384^2 5.51 vs 7.47, 512^2 7.09 vs
+    // 7.73, 640^2 8.60 vs 10.43, 832^2 11.81 vs 13.56, 1024^2 14.80 vs 15.51; 768^2 keeps 6).
+    // The one-step sweep's default shape serves the odd last step.
     h->launch = default_launch(nx, ny);
     {
-        const long long X = nx, Y = ny, strips = (X + 57) / 58;
+        const long long strips = ((long long)nx + 57) / 58;
+        bool small = false;
         h->launch.kernel = pplbm::kKernelSweep2;
-        h->launch.tx = 256;
+        h->launch.ty = pplbm::two_step_height(
+            [&](int rows) { return strips * (((long long)ny + rows - 1) / rows); }, &small);
+        h->launch.tx = small ? 64 : 256;
         h->launch.flags = pplbm::kFlagXCD;  // 4096^2: 167.8 -> 159.2 us per step
-        if (strips * ((Y + 15) / 16) >= 8192) {
-            h->launch.ty = 16;
-        } else if (strips * ((Y + 23) / 24) >= 3072) {
-            h->launch.ty = 24;
-        } else {
-            const long long segs = std::max(1LL, 3200 / strips);
-            h->launch.ty = (int)std::min(24LL, std::max(6LL, (Y + segs - 1) / segs));
-            const long long small = std::max(1LL, (strips * Y + 1023) / 1024);
-            if (h->launch.ty == 6 && small < 6) {
-                h->launch.ty = (int)small;
-                h->launch.tx = 64;
-            }
-        }
     }
     *out = h;
     return LBM_OK;

@@ -97,7 +97,6 @@ size_t tiles_max(const lbm_batch *b, int i) {
     return tiles_at(b, i, b->seg_rows[i] ? b->seg_rows[i] : kAutoRowsMin);
 }
 
-constexpr int kTwoStepRowsMin = 6;  // lowest segment height of the rule on larger batches
 
 size_t tiles2_at(const lbm_batch *b, int i, int rows) {
     const Physics &p = b->phys[i];
@@ -105,29 +104,17 @@ size_t tiles2_at(const lbm_batch *b, int i, int rows) {
     return (size_t)((p.nx + w - 1) / w) * ((p.ny + rows - 1) / rows);
 }
 
-// Segment height of the two-step tiles of the active lattices, by the single lattice's rule
-// on the total wave count (the kinds run side by side): 16 rows where that makes at least 8192
-// waves, else 24 where that makes about 3072, else the lowest height from 6 rows up that makes
-// at most about 3200 (one resident round); where even 6 rows leave fewer, the launch is bound
-// by the latency of each wave's rows and the height falls to about one wave per 1024 rows of
-// strips (at least 1).  As converged lattices leave, the ones still running are cut into
-// shorter segments, so the last few still spread over the GPU.
+// Segment height of the two-step tiles of the active lattices: the single lattice's rule
+// (two_step_height) on the total wave count, the kinds running one after another.  As converged
+// lattices leave, the ones still running are cut into shorter segments, so the last few still
+// spread over the GPU.
 int two_step_rows(const lbm_batch *b) {
-    auto count = [&](int rows) {
+    return pplbm::two_step_height([&](int rows) {
         size_t n = 0;
         for (int i = 0; i < b->count; ++i)
             if (b->active[i]) n += tiles2_at(b, i, rows);
-        return n;
-    };
-    if (count(16) >= 8192) return 16;
-    if (count(24) >= 3072) return 24;
-    for (int rows = kTwoStepRowsMin; rows < 24; ++rows)
-        if (count(rows) <= 3200) {
-            if (rows == kTwoStepRowsMin)
-                return (int)std::min<size_t>(rows, std::max<size_t>(1, (count(1) + 1023) / 1024));
-            return rows;
-        }
-    return 24;
+        return (long long)n;
+    });
 }
 
 bool two_step(const lbm_batch *b) { return b->flags & LBM_LAUNCH_TWO_STEP; }

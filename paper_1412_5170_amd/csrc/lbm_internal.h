@@ -48,6 +48,39 @@ constexpr int kFlagXCD = 2;  // XCD-aware order of the tiles
 constexpr int kFlagShallow = 4;  // sweep: prefetch one row ahead instead of two
 enum { kKernelTwoPass = 0, kKernelSweep = 1, kKernelSweep2 = 2 };
 
+// Segment height of a two-step sweep launch from its wave count W(H) (strips of 58 output
+// columns x segments of H rows, summed over the lattices the launch covers).  Many waves: 16
+// rows where W(16) >= 8192, else 24 where W(24) >= 3072, else the lowest height from 6 rows up
+// with W <= 3200 (one resident round: 4096 wave slots).  Where that is 6 rows the launch cannot
+// fill the GPU and takes as long as its busiest SIMD: about (H + 4) rows of iterations times
+// max(1.5, ceil(W(H) / 1024)) (waves per SIMD; a lone wave issues at about two thirds of the
+// rate of two or more), minimised over H in 1..12 (the larger H on a tie).  Sets *small when
+// the latter rule decided.
+template <typename F>
+int two_step_height(F waves, bool *small = nullptr) {
+    if (small) *small = false;
+    if (waves(16) >= 8192) return 16;
+    if (waves(24) >= 3072) return 24;
+    int h = 24;
+    for (int rows = 6; rows < 24; ++rows)
+        if (waves(rows) <= 3200) {
+            h = rows;
+            break;
+        }
+    if (h > 6) return h;
+    long long best = -1;
+    for (int rows = 1; rows <= 12; ++rows) {
+        const long long k = ((long long)waves(rows) + 1023) / 1024;
+        const long long cost = (rows + 4) * (k < 2 ? 3 : 2 * k);  // 2 (H + 4) max(1.5, k)
+        if (best < 0 || cost <= best) {
+            best = cost;
+            h = rows;
+        }
+    }
+    if (small) *small = true;
+    return h;
+}
+
 // Shape of the step launch.  Two-pass: (tx, ty) is the fused pass's tile.  Sweep: tx columns
 // per workgroup, ty rows per segment.
 struct Launch {

@@ -231,13 +231,13 @@ def test_launch_rules_beyond_4gib():
         assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, 256, ty, lbm.LBM_LAUNCH_XCD_ORDER)
         lbm.lbm_destroy(h)
     # smaller lattices: the segment height that gives about 3200 waves, between 6 and 24 rows;
-    # below about 768^2 one wave per 1024 rows of strips, in workgroups of one wave
-    for n, tx, ty in ((1536, 256, 14), (1024, 256, 6), (768, 256, 6), (512, 64, 5),
-                      (256, 64, 2), (128, 64, 1)):
+    # where that is 6 rows, 1-12 rows by waves per SIMD and rows per wave, one wave per workgroup
+    for n, tx, ty in ((1536, 256, 14), (1152, 256, 8), (1024, 64, 10), (832, 64, 7),
+                      (768, 64, 6), (640, 64, 4), (512, 64, 5), (256, 64, 2), (128, 64, 1)):
         h = create(n, n)
         assert launch(h) == (lbm.LBM_KERNEL_SWEEP2, tx, ty, lbm.LBM_LAUNCH_XCD_ORDER)
         lbm.lbm_destroy(h)
-    tiny = create(300, 130)  # 6 strips x 130 rows: one wave per row
+    tiny = create(300, 130)  # 6 strips x 130 rows: one row per wave
     assert launch(tiny) == (lbm.LBM_KERNEL_SWEEP2, 64, 1, lbm.LBM_LAUNCH_XCD_ORDER)
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 320, 32, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_set_launch(tiny, lbm.LBM_KERNEL_SWEEP2, 256, 24, 0) == lbm.LBM_OK
@@ -248,14 +248,15 @@ def test_default_two_step_heights_follow_the_wave_count():
     """The default segment height of the two-step sweep, on many lattice shapes (host rule, no
     GPU call): 16 rows where that makes at least 8192 waves of 58 columns, else 24 rows where
     that makes at least 3072, else the lowest height from 6 to 24 rows that keeps the wave count
-    at or below about 3200 (one resident round); on small lattices, where 6 rows would be
-    chosen, about one wave per 1024 rows of strips (at least 1 row), one wave per workgroup."""
+    at or below about 3200 (one resident round); where that is 6 rows, the height in 1..12 that
+    minimises (rows + 4) max(1.5, ceil(waves / 1024)), one wave per workgroup."""
     from paper_1412_5170_amd import lbm
     eos, frc, coll = lbm.make_eos(0.6, K=1 / 49), lbm.make_force("GUO_LI", sigma=0.125), \
         lbm.make_collision("BGK")
     rng = np.random.default_rng(7)
     shapes = [(1, 1), (3, 3), (4, 256), (58, 58), (59, 7), (4096, 8), (8, 4096), (100000, 4),
-              (128, 128), (256, 256), (384, 384), (512, 512), (768, 768)]
+              (128, 128), (256, 256), (384, 384), (512, 512), (640, 640), (768, 768),
+              (832, 832), (1024, 1024), (1152, 1152), (1536, 1536)]
     shapes += [tuple(int(v) for v in rng.integers(1, 6000, 2)) for _ in range(40)]
     for nx, ny in shapes:
         h = lbm._P()
@@ -267,16 +268,15 @@ def test_default_two_step_heights_follow_the_wave_count():
         lbm.lbm_destroy(h)
         strips = -(-nx // 58)
         waves = lambda rows: strips * -(-ny // rows)  # noqa: E731
-        small = -(-strips * ny // 1024)
         assert (k, fl) == (lbm.LBM_KERNEL_SWEEP2, lbm.LBM_LAUNCH_XCD_ORDER), (nx, ny)
         if waves(16) >= 8192:
             assert (tx, ty) == (256, 16), (nx, ny, ty)
         elif waves(24) >= 3072:
             assert (tx, ty) == (256, 24), (nx, ny, ty)
-        elif ty < 6:
-            assert (tx, ty) == (64, small) and waves(6) <= 3200, (nx, ny, ty)
+        elif waves(6) <= 3200:
+            cost = {r: (r + 4) * max(1.5, -(-waves(r) // 1024)) for r in range(1, 13)}
+            assert tx == 64 and cost[ty] == min(cost.values()), (nx, ny, ty)
+            assert all(cost[r] > cost[ty] for r in range(ty + 1, 13)), (nx, ny, ty)
         else:
-            assert tx == 256 and ty <= 24, (nx, ny, ty)
-            assert ty == 6 or waves(ty) <= 3200, (nx, ny, ty)
-            assert ty == 6 or waves(ty - 1) > 3200, (nx, ny, ty)
-            assert ty > 6 or small >= 6, (nx, ny, ty)
+            assert tx == 256 and 6 < ty <= 24, (nx, ny, ty)
+            assert waves(ty) <= 3200 and waves(ty - 1) > 3200, (nx, ny, ty)
