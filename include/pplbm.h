@@ -302,7 +302,7 @@ void lbm_batch_destroy(lbm_batch_t *b);
  * captured graph holds one chain of launches, kind after kind, on the batch's stream
  * (LBM_LAUNCH_SERIAL_KINDS is accepted and is the only behaviour).  LBM_LAUNCH_TWO_STEP
  * advances two steps per launch with the single lattice's two-step sweep: one 64-lane wave per
- * tile (a strip of 58 output columns over a segment of 6 to 24 rows, the height chosen at every
+ * tile (a strip of 58 output columns over a segment of 1 to 24 rows, the height chosen at every
  * change of the active set by the single lattice's rule applied to the active lattices' total
  * wave count); with n = 2 mod 4 steps the last two are one-step launches.  Results are bitwise
  * the same in every case.  Default: tx = 256, groups = 0, flags = LBM_LAUNCH_TWO_STEP. */
