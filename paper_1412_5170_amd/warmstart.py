@@ -52,10 +52,11 @@ def features(m):
                      / (0.5 * math.log(K_RANGE[1] / K_RANGE[0]))], dtype=np.float32)
 
 
-def draw_training(seed, count, n_min=96, n_step=16, n_levels=19, K=None):
+def draw_training(seed, count, n_min=96, n_step=16, n_levels=19, K=None, ttc_range=(0.5, 0.9)):
     """Training droplets drawn like the sweep, with K log-uniform in K_RANGE (or every member
     at the given K)."""
-    draw = inputs.batch_draw(seed, count=count, n_min=n_min, n_step=n_step, n_levels=n_levels)
+    draw = inputs.batch_draw(seed, count=count, n_min=n_min, n_step=n_step, n_levels=n_levels,
+                             ttc_range=ttc_range)
     rng = np.random.default_rng(seed + 7919)
     ms = sweep.members_from_draw(draw)
     for m in ms:
@@ -329,6 +330,9 @@ def main(argv=None):
     ap.add_argument("--train-sweep-k-count", type=int, default=0,
                     help="extra training droplets of sizes 384 + 16 k, k < 41, all at the sweep's "
                          "own K (seed 3)")
+    ap.add_argument("--train-cold-count", type=int, default=0,
+                    help="extra training droplets of sizes 384 + 16 k, k < 41, at the sweep's own "
+                         "K and T/Tc in [0.5, 0.65], where the densities change fastest (seed 4)")
     ap.add_argument("--eval-seed", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=64)
     ap.add_argument("--eval-levels", type=int, default=57, help="sizes 128 + 16 k, k < levels")
@@ -365,6 +369,9 @@ def main(argv=None):
         if a.train_sweep_k_count > 0:
             draws.append(draw_training(3, a.train_sweep_k_count, n_min=384, n_levels=41,
                                        K=sweep.PHYSICS["K"]))
+        if a.train_cold_count > 0:
+            draws.append(draw_training(4, a.train_cold_count, n_min=384, n_levels=41,
+                                       K=sweep.PHYSICS["K"], ttc_range=(0.5, 0.65)))
         for tr in draws:
             t0 = time.perf_counter()
             prof, steps, status = equilibria(lbm, tr, a.train_tol, tol_rho=a.train_tol_rho)
