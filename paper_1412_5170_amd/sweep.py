@@ -40,14 +40,17 @@ def tanh_density(lbm, m, W=5.0):
     return inputs.droplet(m["nx"], m["ny"], m["R"], W, l, g)
 
 
-PROFILE_SPACING = 1.5
+PROFILE_SPACING = 2.0
+PROFILE_CENTRE = 23.5  # fractional index of the interface radius
 
 
 def profile_radii(R):
-    """Radii of the 64-point radial profile, centred on the interface radius R:
-    r_k = R + (k - 31.5) h, h = 1.5 lattice units (the interface keeps its width in lattice
-    units whatever R is, so the same network serves every droplet size)."""
-    return R + PROFILE_SPACING * (np.arange(PROFILE_POINTS) - (PROFILE_POINTS - 1) / 2)
+    """Radii of the 64-point radial profile around the interface radius R:
+    r_k = R + (k - 23.5) h, h = 2 lattice units, from 47 nodes inside to 79 outside (the
+    interface keeps its width in lattice units whatever R is, so the same network serves every
+    droplet size).  The vapour side reaches further: at T/Tc = 0.5 and K = 1/49 the vapour 47
+    nodes out is still 10 % above its plateau, 79 nodes out within 0.1 %."""
+    return R + PROFILE_SPACING * (np.arange(PROFILE_POINTS) - PROFILE_CENTRE)
 
 
 def radial_profile(m, rho):

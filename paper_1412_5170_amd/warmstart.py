@@ -2,8 +2,9 @@
 
 A small network (4 -> 128 -> 128 -> 128 -> 64, tanh, FP32, the library's own GPU forward,
 backward and Adam kernels) maps a droplet's (T/Tc, tau, R, K) to its equilibrium radial density
-profile: log rho at 64 radii centred on the initial radius, r_k = R + 1.5 (k - 31.5).  It is
-trained on equilibria that the batched sweep itself produces from plain tanh initial states.
+profile: log rho at 64 radii around the initial radius, r_k = R + 2 (k - 23.5), from 47 nodes
+inside the interface to 79 outside.  It is trained on equilibria that the batched sweep itself
+produces from plain tanh initial states.
 At run time its profile is expanded on the device, shifted radially so that its total mass
 equals that of the tanh state it replaces (in a periodic box the mass fixes the equilibrium),
 and set at physical rest (f = f^eq(rho, -F/(2 rho))); the tanh state is the fallback when a

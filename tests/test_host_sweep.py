@@ -13,11 +13,14 @@ def _member(n=160, R=40.0):
     return dict(sweep.PHYSICS, nx=n, ny=n, R=R, T_over_Tc=0.6, tau=1.0, collision="BGK")
 
 
-def test_profile_radii_are_centred_on_the_interface():
+def test_profile_radii_span_the_interface():
+    """Uniform radii with the interface radius between points 23 and 24, from 47 nodes inside
+    it to 79 outside (the vapour side reaches its plateau further out)."""
     r = sweep.profile_radii(40.0)
     assert len(r) == sweep.PROFILE_POINTS == oprof.POINTS == 64
     assert np.allclose(np.diff(r), sweep.PROFILE_SPACING)
-    assert (r[31] + r[32]) / 2 == pytest.approx(40.0)
+    assert (r[23] + r[24]) / 2 == pytest.approx(40.0)
+    assert r[0] == pytest.approx(40.0 - 47.0) and r[-1] == pytest.approx(40.0 + 79.0)
     assert np.array_equal(r, oprof.radii(r[0], sweep.PROFILE_SPACING))
 
 
