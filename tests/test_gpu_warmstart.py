@@ -145,7 +145,7 @@ def test_trained_network_gain(L):
     Each start runs under a stopping rule 4x tighter than the sweep's, recording the probe
     density ratio every 500 steps; the converged ratio of a lattice is the mean of the tanh and
     learned end points, and a start's cost is the lattice updates until its ratio stays within
-    1e-4 of it.  The network must reach that band with at most 0.7x the tanh start's updates,
+    1e-4 of it.  The network must reach that band with at most 0.6x the tanh start's updates,
     and the constant profile must not do as well as the network."""
     from paper_1412_5170_amd import sweep, warmstart as WS
     members = sweep.members_from_draw(inputs.batch_draw(5, count=8, n_levels=13))
@@ -171,5 +171,5 @@ def test_trained_network_gain(L):
     say(f"    learned / tanh {cost['learned'] / cost['tanh']:.3f}, constant / tanh "
         f"{cost['constant'] / cost['tanh']:.3f}; end-point spread {spread:.1e}")
     assert spread < 1e-4
-    assert cost["learned"] <= 0.7 * cost["tanh"]
+    assert cost["learned"] <= 0.6 * cost["tanh"]
     assert cost["constant"] > cost["learned"]
